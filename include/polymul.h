@@ -1,0 +1,195 @@
+/*
+ * polymul.h -- C ABI of the MI355X (gfx950) sparse polynomial product.
+ *
+ * Operation (Section 2 of Gastineau & Laskar, problem statement and Fig. 1):
+ * for A = sum_i a_i x^{alpha_i} and B = sum_j b_j x^{beta_j}, each stored in
+ * distributed format (a term list sorted by a monomial order), compute
+ *     C = A * B = sum_{i,j} a_i b_j x^{alpha_i + beta_j}
+ * with equal monomials grouped, like terms summed and zero terms dropped, the
+ * result sorted ascending (Algorithm 1 concatenates its sorted containers in
+ * ascending order to obtain the canonical form).  This is Algorithm 1's
+ * mul(A, B, .) without the interval-count argument: how the work is split on
+ * the device is internal.
+ *
+ * Term layout.  A polynomial is two device arrays of equal length n:
+ *   keys[n]   uint64: packed exponent vector.  Variable v (0 <= v < nvars)
+ *             occupies bits [(nvars-1-v)*bits, (nvars-1-v)*bits + bits), so
+ *             variable 0 is the most significant field and the unsigned order
+ *             of keys is the lexicographic monomial order (the paper packs all
+ *             exponents of a term into one 64-bit word, Section 6).  Keys must
+ *             be strictly ascending and bits above nvars*bits must be zero.
+ *   coefs[n]  8 bytes per term, by ring:
+ *             PM_MODP61  uint64 residue in [0, p), p = 2^61 - 1
+ *             PM_F64     IEEE double, finite
+ *             PM_I64     int64 (arithmetic is exact modulo 2^64; the result is
+ *                        the exact integer product when that fits int64)
+ *   Zero input coefficients are allowed; they contribute nothing.
+ * Output keys are strictly ascending; no output coefficient is zero (for
+ * PM_F64: exactly +0.0 or -0.0 is dropped).
+ *
+ * Memory.  All term arrays are device memory owned by the caller and must stay
+ * alive until the stream has executed the call.  The output arrays and the
+ * workspace are caller-allocated device memory; the library allocates no
+ * device memory on the product path.  `n_out` may point to device memory or
+ * to pinned (hipHostMalloc) host memory.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * pm_mul and pm_mul_batch read back a small statistics block (validation
+ * result and per-variable exponent ranges) with one synchronisation of the
+ * stream, then enqueue the product and return: the output arrays and *n_out
+ * are valid once the stream has completed.
+ *
+ * FP64 summation order.  Contributions to one output monomial are added left
+ * to right in row-major (i, j) order of the operands, each product rounded
+ * once; the result is therefore the same whether a product runs alone, in a
+ * batch or through the server, and equals the plain row-major schoolbook sum.
+ *
+ * Errors are negative return codes; see pm_strerror.
+ */
+#ifndef POLYMUL_H
+#define POLYMUL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PM_OK 0
+#define PM_EINVAL (-1)     /* null pointer, bad layout, negative size, key bits outside the fields */
+#define PM_EUNSORTED (-2)  /* input keys not strictly ascending */
+#define PM_EOVERFLOW (-3)  /* max_f[v] + max_g[v] does not fit the field of variable v */
+#define PM_ERANGE (-4)     /* residue >= p (PM_MODP61) or non-finite coefficient (PM_F64) */
+#define PM_ECAPACITY (-5)  /* output capacity below the bound (pm_server_submit only) */
+#define PM_ENOMEM (-6)     /* workspace too small, or server arena cannot ever hold the request */
+#define PM_EDEVICE (-7)    /* HIP runtime error; pm_last_error() has the message */
+#define PM_EBUSY (-8)      /* server: request queue full, retry later */
+
+typedef enum { PM_MODP61 = 0, PM_F64 = 1, PM_I64 = 2 } pm_ring;
+
+/* nvars >= 1, bits >= 1, nvars * bits <= 64; ring one of pm_ring. */
+typedef struct {
+    uint32_t nvars;
+    uint32_t bits;
+    int32_t ring;
+    int32_t reserved; /* must be 0 */
+} pm_layout;
+
+/* Read-only operand: n terms, device pointers (may be NULL when n == 0). */
+typedef struct {
+    int64_t n;
+    const uint64_t *keys;
+    const void *coefs;
+} pm_cpoly;
+
+/* Result: device arrays of `capacity` terms; *n_out receives the term count.
+ * If the product has more than `capacity` terms, the first `capacity` terms
+ * are written and *n_out still receives the full count (so *n_out > capacity
+ * signals truncation).  A capacity of at least the bound from pm_mul_bound
+ * never truncates. */
+typedef struct {
+    int64_t capacity;
+    int64_t *n_out;
+    uint64_t *keys;
+    void *coefs;
+} pm_poly;
+
+/*
+ * Bound on the result size and the workspace size of pm_mul.
+ * max_terms = min(n_f * n_g, prod_v (max_f[v] + max_g[v] - min_f[v] - min_g[v] + 1)):
+ * every output monomial is some alpha_i + beta_j (Fig. 1) and lies in the
+ * degree box of the two operands.  Validates the operands (same codes as
+ * pm_mul).  Synchronises `stream`.
+ */
+int pm_mul_bound(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, int64_t *max_terms,
+                 int64_t *workspace_bytes, void *stream);
+
+/*
+ * h = f * g.  `workspace` is device memory of at least the size returned by
+ * pm_mul_bound for the same operands (256-byte aligned).  Returns PM_OK once
+ * the product is enqueued on `stream`, or an error code (nothing enqueued
+ * that writes h).
+ */
+int pm_mul(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
+           int64_t workspace_bytes, void *stream);
+
+/*
+ * Batched form: `count` independent products h[k] = f[k] * g[k] sharing one
+ * layout, run from a single device work queue of tiles (persistent kernels,
+ * replayed from a HIP graph).  max_terms[k] receives each product's bound;
+ * workspace_bytes the size pm_mul_batch needs for the whole batch.
+ */
+int pm_mul_batch_bound(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                       int64_t *max_terms, int64_t *workspace_bytes, void *stream);
+int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
+                 void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
+ * Serving loop (continuous batching).  The server owns one device arena of
+ * `hbm_budget_bytes`, allocated once at create, and a scheduler thread.  A
+ * submitted product is admitted when its bound-sized workspace fits the free
+ * part of the arena; admitted products are launched in batches on the
+ * server's streams while earlier batches still run, and their memory returns
+ * to the arena when they complete.  Results are identical to pm_mul's.
+ *   create:  nstreams in [1, 8]; returns NULL on failure (see pm_last_error).
+ *   submit:  operands and result arrays as for pm_mul (caller-owned device
+ *            memory; h->capacity must be >= the bound, else PM_ECAPACITY);
+ *            returns a ticket.  PM_ENOMEM if the request can never fit the
+ *            arena, PM_EBUSY if the pending queue is full.
+ *   poll:    *done = 1 once the result is complete and visible on the host;
+ *            *status receives the request's own return code.
+ *   wait:    blocks until the ticket completes.
+ *   stats:   latency (submit -> completion observed by the scheduler) of all
+ *            completed requests, in microseconds, up to `cap` entries.
+ *   destroy: waits for all outstanding work and frees the arena.
+ */
+typedef struct pm_server pm_server;
+pm_server *pm_server_create(int64_t hbm_budget_bytes, int32_t nstreams);
+int pm_server_submit(pm_server *s, const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
+                     uint64_t *ticket);
+int pm_server_poll(pm_server *s, uint64_t ticket, int32_t *done, int32_t *status);
+int pm_server_wait(pm_server *s, uint64_t ticket, int32_t *status);
+int64_t pm_server_latencies(pm_server *s, double *latency_us, int64_t cap);
+void pm_server_destroy(pm_server *s);
+
+/*
+ * Host-only planning (no GPU access): the bound and workspace size that
+ * pm_mul_batch_bound would return for operands with the given term counts
+ * and exponent ranges.  stats holds, for each product k, 4*nvars values:
+ * f's per-variable minima, f's maxima, g's minima, g's maxima.  For callers
+ * that already know these ranges and want to size buffers without a
+ * device round trip.  Returns PM_EOVERFLOW like pm_mul_bound.
+ */
+int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na, const int64_t *nb,
+                       const uint64_t *stats, int64_t *max_terms, int64_t *workspace_bytes);
+
+/*
+ * Process-wide tuning of later calls (the autotuner's knobs):
+ *   tile_cfg     -1 automatic, else 0: 32x64, 1: 64x64, 2: 128x128 term tiles
+ *   force_raw    1: exact rings skip the LDS combine and stage every product
+ *   allow_dense  0: never use the degree-box path
+ * Results do not depend on these settings.
+ */
+int pm_set_tuning(int32_t tile_cfg, int32_t force_raw, int32_t allow_dense);
+
+/*
+ * Synchronises `stream`, then reports whether the last pm_mul / pm_mul_batch
+ * call made by this thread hit an internal consistency check on the device
+ * (a look-back wait that reached its bound, or a radix scatter position
+ * outside its product's range): PM_EDEVICE if so, else PM_OK.  The workspace
+ * of that call must still be allocated.  For tests and debugging.
+ */
+int pm_last_call_status(void *stream);
+
+/* Static message for an error code. */
+const char *pm_strerror(int code);
+/* Message of the last PM_EDEVICE error raised on the calling thread. */
+const char *pm_last_error(void);
+/* Library version string. */
+const char *pm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYMUL_H */

@@ -1,0 +1,349 @@
+// C ABI of the sparse polynomial product (include/polymul.h): argument checks,
+// the validation / statistics round trip, planning and launch.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/polymul.h"
+#include "pm_api_internal.hpp"
+#include "pm_launch.hpp"
+
+namespace pm {
+
+static thread_local std::string g_last_error;
+static thread_local void *g_last_counters = nullptr;
+
+void set_error(const char *what, hipError_t e) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+}
+
+int device_cus() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    });
+    return cus;
+}
+
+HostStage::~HostStage() {
+    if (pin) (void)hipHostFree(pin);
+    if (ev) (void)hipEventDestroy(ev);
+    if (dtmp) (void)hipFree(dtmp);
+}
+
+// Pinned host staging of at least `bytes`; waits until the last upload that
+// read from it has completed.
+int HostStage::reserve(size_t bytes) {
+    if (!ev) {
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            set_error("hipEventCreate", e);
+            return PM_EDEVICE;
+        }
+    }
+    if (used) {
+        hipError_t e = hipEventSynchronize(ev);
+        if (e != hipSuccess) {
+            set_error("hipEventSynchronize", e);
+            return PM_EDEVICE;
+        }
+        used = false;
+    }
+    if (bytes > cap) {
+        if (pin) (void)hipHostFree(pin);
+        pin = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(bytes, 1 << 20);
+        hipError_t e = hipHostMalloc(&pin, want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_error("hipHostMalloc", e);
+            return PM_EDEVICE;
+        }
+        cap = want;
+    }
+    return PM_OK;
+}
+
+int HostStage::device_tmp(size_t bytes, void **out) {
+    if (bytes > dtmp_cap) {
+        if (dtmp) (void)hipFree(dtmp);
+        dtmp = nullptr;
+        dtmp_cap = 0;
+        hipError_t e = hipMalloc(&dtmp, bytes);
+        if (e != hipSuccess) {
+            set_error("hipMalloc", e);
+            return PM_EDEVICE;
+        }
+        dtmp_cap = bytes;
+    }
+    *out = dtmp;
+    return PM_OK;
+}
+
+static int check_layout(const pm_layout *L) {
+    if (!L) return PM_EINVAL;
+    if (L->nvars < 1 || L->bits < 1 || (uint64_t)L->nvars * L->bits > 64) return PM_EINVAL;
+    if (L->ring != PM_MODP61 && L->ring != PM_F64 && L->ring != PM_I64) return PM_EINVAL;
+    if (L->reserved != 0) return PM_EINVAL;
+    return PM_OK;
+}
+
+static int check_operand(const pm_cpoly *p) {
+    if (!p || p->n < 0) return PM_EINVAL;
+    if (p->n > 0 && (!p->keys || !p->coefs)) return PM_EINVAL;
+    return PM_OK;
+}
+
+int check_args(const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h) {
+    int rc = check_layout(L);
+    if (rc) return rc;
+    if (count < 0 || count > (int64_t)1 << 24) return PM_EINVAL;
+    if (count > 0 && (!f || !g)) return PM_EINVAL;
+    for (int64_t q = 0; q < count; q++) {
+        if ((rc = check_operand(f + q)) || (rc = check_operand(g + q))) return rc;
+        if (h) {
+            const pm_poly &o = h[q];
+            if (!o.n_out || o.capacity < 0) return PM_EINVAL;
+            if (o.capacity > 0 && (!o.keys || !o.coefs)) return PM_EINVAL;
+        }
+    }
+    return PM_OK;
+}
+
+// Validation + statistics round trip and planning for `count` products.
+// `dev` is device memory of at least stats_region_bytes + sizeof(DevSeg)*count.
+int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                   void *dev, hipStream_t st, const Tuning &tune, Plan &P) {
+    const int S = (int)count, nv = (int)L->nvars;
+    const size_t sreg = stats_region_bytes(S, nv);
+    const size_t segb = sizeof(DevSeg) * S;
+    const size_t sb = stats_bytes(S, nv), fb = (size_t)S * 2 * 4;
+    const size_t up_off = 0, dn_off = (segb + 255) & ~(size_t)255;
+    int rc = hs.reserve(dn_off + sreg);
+    if (rc) return rc;
+    DevSeg *hseg = (DevSeg *)((char *)hs.pin + up_off);
+    std::vector<SegInput> in(S);
+    for (int q = 0; q < S; q++) {
+        DevSeg d = DevSeg();
+        d.fk = f[q].keys;
+        d.fc = (const u64 *)f[q].coefs;
+        d.gk = g[q].keys;
+        d.gc = (const u64 *)g[q].coefs;
+        d.na = f[q].n;
+        d.nb = g[q].n;
+        hseg[q] = d;
+        in[q] = SegInput{d.fk, d.fc, d.gk, d.gc, d.na, d.nb};
+    }
+    char *dbase = (char *)dev;
+    hipError_t e = hipMemcpyAsync(dbase + sreg, hseg, segb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_stats((const DevSeg *)(dbase + sreg), S, nv, (int)L->bits, L->ring, (u64 *)dbase,
+                                          (u32 *)(dbase + ((sb + 255) & ~(size_t)255)), st);
+    char *hstats = (char *)hs.pin + dn_off;
+    if (e == hipSuccess) e = hipMemcpyAsync(hstats, dbase, sreg, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_error("validation", e);
+        return PM_EDEVICE;
+    }
+    (void)fb;
+    return plan_build(nv, (int)L->bits, L->ring, in, (const uint64_t *)hstats,
+                      (const uint32_t *)(hstats + ((sb + 255) & ~(size_t)255)), tune, P);
+}
+
+// Upload the descriptor block of plan P (output pointers filled) and enqueue
+// the pipeline.
+int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st) {
+    for (int q = 0; q < P.nseg; q++) {
+        P.segs[q].hk = h[q].keys;
+        P.segs[q].hc = (u64 *)h[q].coefs;
+        P.segs[q].n_out = h[q].n_out;
+        P.segs[q].cap = h[q].capacity;
+    }
+    int rc = hs.reserve(P.r_desc.bytes);
+    if (rc) return rc;
+    char *pin = (char *)hs.pin;
+    const size_t d0 = P.r_desc.off;
+    memcpy(pin + (P.o_segs - d0), P.segs.data(), sizeof(DevSeg) * P.nseg);
+    if (!P.vars.empty()) memcpy(pin + (P.o_vars - d0), P.vars.data(), sizeof(VarParam) * P.vars.size());
+    memcpy(pin + (P.o_tile_pre - d0), P.tile_pre.data(), 8 * P.tile_pre.size());
+    if (!P.tile_seg.empty()) memcpy(pin + (P.o_tile_seg - d0), P.tile_seg.data(), 4 * P.tile_seg.size());
+    memcpy(pin + (P.o_raw_pre - d0), P.raw_pre.data(), 8 * P.raw_pre.size());
+    if (!P.raw_seg.empty()) memcpy(pin + (P.o_raw_seg - d0), P.raw_seg.data(), 4 * P.raw_seg.size());
+    memcpy(pin + (P.o_dpart_pre - d0), P.dpart_pre.data(), 8 * P.dpart_pre.size());
+    if (!P.dseg.empty()) memcpy(pin + (P.o_dseg - d0), P.dseg.data(), 4 * P.dseg.size());
+    memcpy(pin + (P.o_cpre - d0), P.cpre.data(), 8 * P.cpre.size());
+    hipError_t e = hipMemcpyAsync((char *)ws + d0, pin, P.r_desc.bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(hs.ev, st);
+    if (e != hipSuccess) {
+        set_error("descriptor upload", e);
+        return PM_EDEVICE;
+    }
+    hs.used = true;
+    g_last_counters = (char *)ws + P.o_counters;
+    Ctx C = make_ctx(P, ws);
+    e = launch_pipeline(P, C, st, device_cus());
+    if (e != hipSuccess) {
+        set_error("kernel launch", e);
+        return PM_EDEVICE;
+    }
+    return PM_OK;
+}
+
+static std::mutex g_mu;
+static HostStage g_stage;
+static Tuning g_tune;
+
+Tuning &default_tuning() { return g_tune; }
+
+int bound_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+               int64_t *max_terms, int64_t *ws_bytes, hipStream_t st, const Tuning &tune) {
+    if (count == 0) {
+        if (ws_bytes) *ws_bytes = 0;
+        return PM_OK;
+    }
+    const size_t need = stats_region_bytes((int)count, (int)L->nvars) + sizeof(DevSeg) * count;
+    void *dev = nullptr;
+    int rc = hs.device_tmp(need, &dev);
+    if (rc) return rc;
+    Plan P;
+    rc = stats_and_plan(hs, L, count, f, g, dev, st, tune, P);
+    if (rc) return rc;
+    if (max_terms)
+        for (int64_t q = 0; q < count; q++) max_terms[q] = P.bound[q];
+    if (ws_bytes) *ws_bytes = (int64_t)P.total;
+    return PM_OK;
+}
+
+int mul_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+             const pm_poly *h, void *ws, int64_t ws_bytes, hipStream_t st, const Tuning &tune, Plan *plan_out) {
+    if (count == 0) return PM_OK;
+    const size_t need0 = stats_region_bytes((int)count, (int)L->nvars) + sizeof(DevSeg) * count;
+    if (!ws || ws_bytes < (int64_t)need0) return PM_ENOMEM;
+    Plan P;
+    int rc = stats_and_plan(hs, L, count, f, g, ws, st, tune, P);
+    if (rc) return rc;
+    if ((int64_t)P.total > ws_bytes) return PM_ENOMEM;
+    rc = upload_and_launch(hs, P, h, ws, st);
+    if (plan_out) *plan_out = P;
+    return rc;
+}
+
+}  // namespace pm
+
+using namespace pm;
+
+extern "C" {
+
+int pm_mul_bound(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, int64_t *max_terms,
+                 int64_t *workspace_bytes, void *stream) {
+    int rc = check_args(layout, 1, f, g, nullptr);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return bound_impl(g_stage, layout, 1, f, g, max_terms, workspace_bytes, (hipStream_t)stream, g_tune);
+}
+
+int pm_mul(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
+           int64_t workspace_bytes, void *stream) {
+    int rc = check_args(layout, 1, f, g, h);
+    if (rc) return rc;
+    if (!h) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return mul_impl(g_stage, layout, 1, f, g, h, workspace, workspace_bytes, (hipStream_t)stream, g_tune, nullptr);
+}
+
+int pm_mul_batch_bound(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                       int64_t *max_terms, int64_t *workspace_bytes, void *stream) {
+    int rc = check_args(layout, count, f, g, nullptr);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return bound_impl(g_stage, layout, count, f, g, max_terms, workspace_bytes, (hipStream_t)stream, g_tune);
+}
+
+int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
+                 void *workspace, int64_t workspace_bytes, void *stream) {
+    int rc = check_args(layout, count, f, g, h);
+    if (rc) return rc;
+    if (count > 0 && !h) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return mul_impl(g_stage, layout, count, f, g, h, workspace, workspace_bytes, (hipStream_t)stream, g_tune,
+                    nullptr);
+}
+
+int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na, const int64_t *nb,
+                       const uint64_t *stats, int64_t *max_terms, int64_t *workspace_bytes) {
+    int rc = check_layout(layout);
+    if (rc) return rc;
+    if (count < 0 || (count > 0 && (!na || !nb || !stats))) return PM_EINVAL;
+    std::vector<SegInput> in(count);
+    for (int64_t q = 0; q < count; q++) {
+        if (na[q] < 0 || nb[q] < 0) return PM_EINVAL;
+        in[q] = SegInput{nullptr, nullptr, nullptr, nullptr, na[q], nb[q]};
+    }
+    std::vector<uint32_t> flags(2 * count, 0);
+    Plan P;
+    rc = plan_build((int)layout->nvars, (int)layout->bits, layout->ring, in, stats, flags.data(), g_tune, P);
+    if (rc) return rc;
+    if (max_terms)
+        for (int64_t q = 0; q < count; q++) max_terms[q] = P.bound[q];
+    if (workspace_bytes) *workspace_bytes = (int64_t)P.total;
+    return PM_OK;
+}
+
+int pm_set_tuning(int32_t tile_cfg, int32_t force_raw, int32_t allow_dense) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (tile_cfg < -1 || tile_cfg >= N_TILE_CFGS) return PM_EINVAL;
+    g_tune.tile_cfg = tile_cfg;
+    g_tune.force_raw = force_raw ? 1 : 0;
+    g_tune.allow_dense = allow_dense ? 1 : 0;
+    return PM_OK;
+}
+
+const char *pm_strerror(int code) {
+    switch (code) {
+        case PM_OK: return "ok";
+        case PM_EINVAL: return "invalid argument (null pointer, bad layout, negative size or key bits outside the fields)";
+        case PM_EUNSORTED: return "operand keys are not strictly ascending";
+        case PM_EOVERFLOW: return "exponent sum does not fit its field";
+        case PM_ERANGE: return "coefficient out of range (residue >= 2^61-1 or non-finite double)";
+        case PM_ECAPACITY: return "output capacity below the result bound";
+        case PM_ENOMEM: return "workspace or arena too small";
+        case PM_EDEVICE: return "HIP runtime error";
+        case PM_EBUSY: return "server queue full";
+        default: return "unknown error";
+    }
+}
+
+const char *pm_last_error(void) { return g_last_error.c_str(); }
+
+int pm_last_call_status(void *stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("hipStreamSynchronize", e);
+        return PM_EDEVICE;
+    }
+    if (!g_last_counters) return PM_OK;
+    uint32_t flag = 0;
+    e = hipMemcpy(&flag, (char *)g_last_counters + 4 * CNT_ERR_SPIN, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        set_error("hipMemcpy", e);
+        return PM_EDEVICE;
+    }
+    if (flag) {
+        g_last_error = std::string("device consistency check failed, flags ") + std::to_string(flag);
+        return PM_EDEVICE;
+    }
+    return PM_OK;
+}
+
+const char *pm_version(void) { return "polymul-gfx950 1.0"; }
+
+}  // extern "C"

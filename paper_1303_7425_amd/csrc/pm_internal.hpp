@@ -1,0 +1,312 @@
+// Internal definitions shared by the host planner and the gfx950 kernels of
+// the sparse polynomial product.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pm {
+
+typedef uint64_t u64;
+typedef int64_t i64;
+typedef uint32_t u32;
+typedef int32_t i32;
+
+constexpr u64 P61 = (1ull << 61) - 1;
+
+enum Ring : int { RING_MODP = 0, RING_F64 = 1, RING_I64 = 2 };
+
+// How one product (a "segment" of a launch) is computed.
+enum SegMode : int {
+    SEG_EMPTY = 0,    // an operand is empty: n_out = 0
+    SEG_COMBINE = 1,  // tiles combined in LDS, then global radix sort + segmented reduction
+    SEG_RAW = 2,      // every term product staged in row-major order, then sort + reduction
+    SEG_DENSE = 3,    // accumulated directly into the degree box, then compaction
+};
+
+constexpr int NTHREADS = 256;          // threads per workgroup (4 wave64s)
+constexpr int IPT = 16;                // items per thread in sort / reduce partitions
+constexpr int PART = NTHREADS * IPT;   // items per partition
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int MAX_PASSES = 8;
+constexpr int MAX_VARS = 64;
+
+// Per-product descriptor, uploaded once per call.
+struct DevSeg {
+    const u64 *fk, *fc, *gk, *gc;  // operand keys / coefficient bits
+    i64 na, nb;
+    i64 ck_f, ck_g;                // offsets of the compressed operand keys
+    i64 stage_base;                // first staging slot (sparse) or first box cell (dense)
+    i64 stage_bound;               // staging slots (sparse) or box cells (dense)
+    i64 tile_first;                // first tile of this product in the tile queue
+    i64 tiles_n;                   // tiles along g
+    i64 raw_first;                 // first row-chunk block (SEG_RAW)
+    i64 raw_chunks;                // row chunks per row (SEG_RAW)
+    i64 dpart_first;               // first compaction partition (SEG_DENSE)
+    i64 var_off;                   // offset of this product's VarParam entries
+    u64 lo_key;                    // packed key of the smallest output exponent vector
+    u64 *hk, *hc;                  // result arrays
+    i64 *n_out;
+    i64 cap;
+    i32 mode;
+    i32 pad;
+};
+
+// Values produced on the device during a call.
+struct DevSegDyn {
+    unsigned long long fill;       // staged pairs (SEG_COMBINE)
+    i64 n;                         // pairs to sort
+    i64 part_first;                // first sort / reduce partition
+    i64 nparts;
+};
+
+// Per product and variable: field position and the mixed-radix compression.
+// compressed(alpha) = sum_v (alpha_v - min_v) * stride_v, strides taken over the
+// output ranges range_v = max_f+max_g-min_f-min_g+1, so compressed(f_i) +
+// compressed(g_j) is the mixed-radix index of alpha_i+beta_j in the degree box
+// and preserves the lexicographic order.
+struct VarParam {
+    u32 shift;
+    u32 pad;
+    u64 mask;
+    u64 minf, ming;
+    u64 range;
+    u64 stride;
+};
+
+// Launch-wide context passed by value to every kernel.
+struct Ctx {
+    DevSeg *segs;
+    DevSegDyn *dyn;
+    VarParam *vars;
+    const i64 *tile_pre;    // [ntseg+1] exclusive tile prefix over tiled segments
+    const i32 *tile_seg;    // [ntseg] segment index of each tiled segment
+    const i64 *raw_pre;     // [nrseg+1] row-chunk block prefix over SEG_RAW segments
+    const i32 *raw_seg;
+    const i64 *dpart_pre;   // [ndseg+1] compaction partition prefix over SEG_DENSE segments
+    const i32 *dseg;
+    i64 *ppre;              // [nseg+1] sort partition prefix (device computed)
+    void *ck;               // compressed operand keys
+    void *stA_k; u64 *stA_v;
+    void *stB_k; u64 *stB_v;
+    u64 *box;
+    unsigned long long *hist;   // [passes][nseg][RADIX]
+    u64 *bases;                 // [passes][nseg][RADIX]
+    u64 *look;                  // sort lookback [nparts_bound][RADIX]
+    u64 *look_red;              // reduce lookback [nparts_bound]
+    u64 *look_cmp;              // dense compaction lookback [ndparts]
+    u32 *counters;              // work-queue tickets and error flags
+    i32 nseg, ntseg, nrseg, ndseg;
+    i32 nvars, bits, passes, ring;
+    i64 ntiles, nraw, ndparts;
+};
+
+// counters[] slots
+enum Counter : int {
+    CNT_TILE = 0,
+    CNT_RAW = 1,
+    CNT_SORT = 2,                   // + pass (MAX_PASSES slots)
+    CNT_REDUCE = CNT_SORT + MAX_PASSES,
+    CNT_COMPACT,
+    CNT_ERR_SPIN,                   // a lookback wait hit its iteration bound
+    CNT_COUNT
+};
+
+// Validation flags reported by the statistics kernel.
+enum StatFlag : u32 { ST_UNSORTED = 1, ST_BADBITS = 2, ST_RANGE = 4 };
+
+// ---------------------------------------------------------------------------
+// Ring arithmetic on 64-bit coefficient words
+// ---------------------------------------------------------------------------
+__host__ __device__ inline u64 addmod61(u64 a, u64 b) {
+    u64 s = a + b;  // < 2^62
+    return s >= P61 ? s - P61 : s;
+}
+
+// a * b mod 2^61-1 for a, b < 2^61: the 122-bit product is split at bit 61 and
+// folded twice (2^61 = 1 mod p).
+__device__ inline u64 mulmod61(u64 a, u64 b) {
+    u64 lo = a * b;
+    u64 hi = __umul64hi(a, b);
+    u64 r = (lo & P61) + ((lo >> 61) | (hi << 3));
+    r = (r & P61) + (r >> 61);
+    return r >= P61 ? r - P61 : r;
+}
+
+// Any u64 to its residue in [0, p).
+__host__ __device__ inline u64 reduce61(u64 x) {
+    u64 r = (x & P61) + (x >> 61);
+    return r >= P61 ? r - P61 : r;
+}
+
+template <int RING>
+__device__ inline u64 ring_mul(u64 a, u64 b) {
+    if constexpr (RING == RING_MODP) {
+        return mulmod61(a, b);
+    } else if constexpr (RING == RING_I64) {
+        return a * b;  // two's-complement product modulo 2^64
+    } else {
+        return (u64)__double_as_longlong(__longlong_as_double((long long)a) * __longlong_as_double((long long)b));
+    }
+}
+
+template <int RING>
+__device__ inline u64 ring_add(u64 a, u64 b) {
+    if constexpr (RING == RING_MODP) {
+        return addmod61(a, b);
+    } else if constexpr (RING == RING_I64) {
+        return a + b;
+    } else {
+        return (u64)__double_as_longlong(__longlong_as_double((long long)a) + __longlong_as_double((long long)b));
+    }
+}
+
+template <int RING>
+__device__ inline bool ring_is_zero(u64 a) {
+    if constexpr (RING == RING_F64) {
+        return (a << 1) == 0;  // +0.0 or -0.0
+    } else {
+        return a == 0;
+    }
+}
+
+// Order-free exact accumulation into a 64-bit cell (LDS or global).
+//   mod p: the cell holds a value congruent to the sum; a wrap past 2^64 is
+//          compensated by adding 8, since 2^64 = 8 (mod 2^61-1).
+//   int64: plain wrapping addition.
+template <int RING>
+__device__ inline void ring_atomic_acc(u64 *cell, u64 c) {
+    if constexpr (RING == RING_MODP) {
+        u64 add = c;
+        while (true) {
+            u64 old = atomicAdd((unsigned long long *)cell, (unsigned long long)add);
+            if (old + add >= old) break;
+            add = 8;
+        }
+    } else {
+        atomicAdd((unsigned long long *)cell, (unsigned long long)c);
+    }
+}
+
+template <int RING>
+__device__ inline u64 ring_cell_final(u64 x) {
+    if constexpr (RING == RING_MODP) {
+        return reduce61(x);
+    } else {
+        return x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 / workgroup primitives
+// ---------------------------------------------------------------------------
+__device__ inline u32 lane_id() { return __lane_id(); }
+
+// popcount(mask & lanes below this one)
+__device__ inline u32 mbcnt(u64 mask) {
+    return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+}
+
+template <typename T>
+__device__ inline T wave_incl_scan(T x) {
+    const u32 lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = __shfl_up(x, d, 64);
+        if (lane >= (u32)d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over the 256 threads of a workgroup.  `scratch` holds 4 T.
+// Contains two barriers; every thread must call it.
+template <typename T>
+__device__ inline T block_excl_scan(T v, T *scratch, T &total) {
+    const u32 lane = lane_id();
+    const u32 w = threadIdx.x >> 6;
+    T x = wave_incl_scan(v);
+    if (lane == 63) scratch[w] = x;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NTHREADS / 64; i++) {
+        T s = scratch[i];
+        if ((u32)i < w) pre += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+// Lookback words: [63:56] tag, [55:54] flag, [53:0] value.
+constexpr u64 LB_AGG = 1, LB_INC = 2;
+__device__ inline u64 lb_pack(u32 tag, u64 flag, u64 value) { return ((u64)tag << 56) | (flag << 54) | value; }
+__device__ inline void lb_store(u64 *p, u64 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline u64 lb_load(u64 *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+constexpr u32 LB_SPIN_LIMIT = 1u << 24;
+
+// Decoupled look-back: exclusive prefix of `value` over partitions
+// [first, p) that published under `tag`.  Partition p publishes its own
+// aggregate first, then its inclusive prefix.  Work-queue order guarantees
+// that every earlier partition belongs to a running or finished workgroup.
+__device__ inline u64 lookback(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
+    if (p == first) {
+        lb_store(look + p * stride, lb_pack(tag, LB_INC, value));
+        return 0;
+    }
+    lb_store(look + p * stride, lb_pack(tag, LB_AGG, value));
+    u64 prefix = 0;
+    i64 j = p - 1;
+    u32 spins = 0;
+    while (true) {
+        u64 v = lb_load(look + j * stride);
+        if ((u32)(v >> 56) != tag) {
+            if (++spins > LB_SPIN_LIMIT) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        prefix += v & ((1ull << 54) - 1);
+        if (((v >> 54) & 3) == LB_INC || j == first) break;
+        j--;
+    }
+    lb_store(look + p * stride, lb_pack(tag, LB_INC, prefix + value));
+    return prefix;
+}
+
+// Largest index s in [0, n) with pre[s] <= x (pre ascending, pre[0] = 0).
+__device__ inline i32 seg_search(const i64 *pre, i32 n, i64 x) {
+    i32 lo = 0, hi = n - 1;
+    while (lo < hi) {
+        i32 mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Mixed-radix index back to the packed key.
+template <typename K>
+__device__ inline u64 decompress(K ck, const VarParam *vp, int nvars, u64 lo_key) {
+    u64 key = lo_key;
+    for (int v = nvars - 1; v >= 0; v--) {
+        K r = (K)vp[v].range;
+        K e;
+        if (r == 0) {  // range 2^64: a single full-width variable
+            e = ck;
+            ck = 0;
+        } else {
+            e = ck % r;
+            ck /= r;
+        }
+        key += (u64)e << vp[v].shift;
+    }
+    return key;
+}
+
+}  // namespace pm

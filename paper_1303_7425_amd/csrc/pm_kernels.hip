@@ -1,0 +1,759 @@
+// gfx950 kernels of the sparse polynomial product h = f * g.
+//
+// Pipeline for one launch (a batch of one or more products, "segments"):
+//   k_stats      validation + per-variable exponent ranges of every operand
+//   k_compress   operand keys -> mixed-radix indices in the product's degree box
+//   k_tile       f-block x g-block tile of term products expanded into LDS and
+//                combined there with an LDS hash (exact rings); unique pairs go
+//                to a staging buffer (sparse) or into the degree-box array (dense)
+//   k_expand_raw every term product staged in row-major (i, j) order (FP64)
+//   k_seg_prepare / k_seg_bases   per-product sizes, partitions, digit offsets
+//   k_onesweep   one stable LSD radix pass (8-bit digit) with decoupled look-back
+//   k_reduce     segmented like-term reduction + zero drop + key decompression
+//   k_compact    dense path: degree-box cells -> sorted non-zero terms
+//
+// The schoolbook product P = sum_{i,j} a_i b_j x^{alpha_i + beta_j} and the
+// canonical (sorted, summed, zero-free) result are defined in Section 2 of the
+// paper (problem statement, Fig. 1, Algorithm 1).  The paper's own GPU kernel
+// builds a per-interval 16-ary tree with atomics (Section 6.3); here the merge
+// and sort step is redesigned for CDNA4 as LDS combine + global radix sort.
+#include "pm_internal.hpp"
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// k_stats: one workgroup per (segment, operand side).  Per-variable min/max of
+// the exponents, strict ascending order, key bits outside the fields, and
+// coefficient range.  out[(q*2+side)*2*nvars + v] = min, [... + nvars + v] = max.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTHREADS) void k_stats(const DevSeg *segs, int nvars, int bits, int ring, u64 *out,
+                                                     u32 *flags) {
+    const int q = blockIdx.x >> 1, side = blockIdx.x & 1;
+    const DevSeg s = segs[q];
+    const i64 n = side ? s.nb : s.na;
+    const u64 *k = side ? s.gk : s.fk;
+    const u64 *c = side ? s.gc : s.fc;
+    const u64 mask = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+    const int used = nvars * bits;
+    __shared__ u64 s_mn[NTHREADS / 64], s_mx[NTHREADS / 64];
+    __shared__ u32 s_flag;
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    u32 fl = 0;
+    for (i64 i = threadIdx.x; i < n; i += NTHREADS) {
+        u64 key = k[i];
+        if (used < 64 && (key >> used) != 0) fl |= ST_BADBITS;
+        if (i > 0 && !(key > k[i - 1])) fl |= ST_UNSORTED;
+        u64 cv = c[i];
+        if (ring == RING_MODP && cv >= P61) fl |= ST_RANGE;
+        if (ring == RING_F64 && ((cv >> 52) & 0x7ff) == 0x7ff) fl |= ST_RANGE;
+    }
+    if (fl) atomicOr(&s_flag, fl);
+    u64 *o = out + (i64)(q * 2 + side) * 2 * nvars;
+    for (int v = 0; v < nvars; v++) {
+        const u32 sh = (u32)((nvars - 1 - v) * bits);
+        u64 mn = ~0ull, mx = 0;
+        for (i64 i = threadIdx.x; i < n; i += NTHREADS) {
+            u64 e = (k[i] >> sh) & mask;
+            mn = e < mn ? e : mn;
+            mx = e > mx ? e : mx;
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            u64 a = __shfl_xor(mn, d, 64), b = __shfl_xor(mx, d, 64);
+            mn = a < mn ? a : mn;
+            mx = b > mx ? b : mx;
+        }
+        if (lane_id() == 0) {
+            s_mn[threadIdx.x >> 6] = mn;
+            s_mx[threadIdx.x >> 6] = mx;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < NTHREADS / 64; w++) {
+                mn = s_mn[w] < mn ? s_mn[w] : mn;
+                mx = s_mx[w] > mx ? s_mx[w] : mx;
+            }
+            o[v] = mn;
+            o[nvars + v] = mx;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flags[q * 2 + side] = s_flag;
+}
+
+// ---------------------------------------------------------------------------
+// Fill a u64 region (the per-call zeroed state: counters, histograms,
+// look-back words, dense box).  A kernel, so that graph replays stay valid.
+// ---------------------------------------------------------------------------
+__global__ void k_fill(u64 *p, i64 n, u64 v) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// k_compress: operand keys -> mixed-radix index.  Term t of the flattened list
+// [seg0.f, seg0.g, seg1.f, ...] located through cpre (exclusive prefix).
+// ---------------------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(NTHREADS) void k_compress(Ctx C, const i64 *cpre, i64 total) {
+    for (i64 t = (i64)blockIdx.x * NTHREADS + threadIdx.x; t < total; t += (i64)gridDim.x * NTHREADS) {
+        i32 idx = seg_search(cpre, 2 * C.nseg, t);
+        const int q = idx >> 1, side = idx & 1;
+        const DevSeg &s = C.segs[q];
+        const i64 i = t - cpre[idx];
+        const u64 key = side ? s.gk[i] : s.fk[i];
+        const VarParam *vp = C.vars + s.var_off;
+        u64 ck = 0;
+        for (int v = 0; v < C.nvars; v++) {
+            u64 e = (key >> vp[v].shift) & vp[v].mask;
+            ck += (e - (side ? vp[v].ming : vp[v].minf)) * vp[v].stride;
+        }
+        ((K *)C.ck)[(side ? s.ck_g : s.ck_f) + i] = (K)ck;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-pass digit histogram kept in LDS across the work items of one segment
+// and flushed to the global [pass][segment][digit] table.
+// ---------------------------------------------------------------------------
+__device__ inline void hist_flush(Ctx &C, u32 *s_hist, int q) {
+    for (int e = threadIdx.x; e < C.passes * RADIX; e += NTHREADS) {
+        u32 v = s_hist[e];
+        if (v) {
+            const int p = e / RADIX, d = e % RADIX;
+            atomicAdd(C.hist + ((i64)p * C.nseg + q) * RADIX + d, (unsigned long long)v);
+            s_hist[e] = 0;
+        }
+    }
+}
+
+template <typename K>
+__device__ inline void hist_add(u32 *s_hist, int passes, K ck) {
+    for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p * RADIX + (u32)((ck >> (p * RADIX_BITS)) & (RADIX - 1))], 1u);
+}
+
+constexpr int MAX_PROBE = 32;
+
+template <typename K>
+__device__ inline K lds_cas(K *p, K cmp, K val) {
+    if constexpr (sizeof(K) == 4) {
+        return (K)atomicCAS((unsigned int *)p, (unsigned int)cmp, (unsigned int)val);
+    } else {
+        return (K)atomicCAS((unsigned long long *)p, (unsigned long long)cmp, (unsigned long long)val);
+    }
+}
+
+template <typename K>
+__device__ inline u32 hash_slot(K ck, int hb) {
+    if constexpr (sizeof(K) == 4) {
+        return ((u32)ck * 2654435761u) >> (32 - hb);
+    } else {
+        return (u32)(((u64)ck * 0x9E3779B97F4A7C15ull) >> (64 - hb));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_tile: persistent work queue over the tiles of all SEG_COMBINE / SEG_DENSE
+// products.  A tile is rows [i0, i0+TM) of f times columns [j0, j0+TN) of g:
+// a TM x TN block of the pp-matrix (Fig. 1).  Each term product is inserted
+// into an LDS open-addressing table keyed by its mixed-radix monomial index
+// and accumulated there exactly (mod p or modulo 2^64).  The table's non-zero
+// entries then go either to the product's staging region (sparse; the region
+// offset is reserved with one atomic per tile, order irrelevant for exact
+// rings) or into the degree-box array (dense).
+// ---------------------------------------------------------------------------
+template <typename K, int RING, int TM, int TN, int HB>
+__global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
+    constexpr int HS = 1 << HB;
+    constexpr int SPT = HS / NTHREADS;
+    const K EMPTY = (K)~(K)0;
+    __shared__ K s_fk[TM], s_gk[TN];
+    __shared__ u64 s_fc[TM], s_gc[TN];
+    __shared__ K s_hk[HS];
+    __shared__ u64 s_hv[HS];
+    __shared__ u32 s_hist[MAX_PASSES * RADIX];
+    __shared__ u32 s_scan[NTHREADS / 64];
+    __shared__ i64 s_tile;
+    __shared__ u64 s_base;
+
+    for (int e = threadIdx.x; e < C.passes * RADIX; e += NTHREADS) s_hist[e] = 0;
+    int cur_q = -1;
+    while (true) {
+        if (threadIdx.x == 0) s_tile = (i64)atomicAdd(&C.counters[CNT_TILE], 1u);
+        __syncthreads();
+        const i64 t = s_tile;
+        if (t >= C.ntiles) break;
+        const i32 ts = seg_search(C.tile_pre, C.ntseg, t);
+        const int q = C.tile_seg[ts];
+        const DevSeg &s = C.segs[q];
+        const i64 local = t - C.tile_pre[ts];
+        const i64 i0 = (local / s.tiles_n) * TM, j0 = (local % s.tiles_n) * TN;
+        const int tm = (int)min((i64)TM, s.na - i0), tn = (int)min((i64)TN, s.nb - j0);
+        const bool dense = s.mode == SEG_DENSE;
+        if (!dense && q != cur_q) {
+            if (cur_q >= 0) hist_flush(C, s_hist, cur_q);
+            cur_q = q;
+        }
+        const K *ck = (const K *)C.ck;
+        for (int e = threadIdx.x; e < TM; e += NTHREADS)
+            if (e < tm) {
+                s_fk[e] = ck[s.ck_f + i0 + e];
+                s_fc[e] = s.fc[i0 + e];
+            }
+        for (int e = threadIdx.x; e < TN; e += NTHREADS)
+            if (e < tn) {
+                s_gk[e] = ck[s.ck_g + j0 + e];
+                s_gc[e] = s.gc[j0 + e];
+            }
+        for (int e = threadIdx.x; e < HS; e += NTHREADS) {
+            s_hk[e] = EMPTY;
+            s_hv[e] = 0;
+        }
+        __syncthreads();
+        // expand + combine
+        for (int e = threadIdx.x; e < TM * TN; e += NTHREADS) {
+            const int i = e / TN, j = e % TN;
+            if (i >= tm || j >= tn) continue;
+            const u64 c = ring_mul<RING>(s_fc[i], s_gc[j]);
+            if (c == 0) continue;
+            const K key = s_fk[i] + s_gk[j];
+            u32 h = hash_slot<K>(key, HB);
+            bool found = false;
+            for (int probe = 0; probe < MAX_PROBE; probe++) {
+                K old = lds_cas<K>(&s_hk[h], EMPTY, key);
+                if (old == EMPTY || old == key) {
+                    found = true;
+                    break;
+                }
+                h = (h + 1) & (HS - 1);
+            }
+            if (found) {
+                ring_atomic_acc<RING>(&s_hv[h], c);
+            } else if (dense) {
+                // table region saturated: accumulate this product in the box directly
+                ring_atomic_acc<RING>(C.box + s.stage_base + (u64)key, c);
+            } else {
+                // stage the single product; the global reduction merges it later
+                const i64 slot = s.stage_base + (i64)atomicAdd(&C.dyn[q].fill, 1ull);
+                ((K *)C.stA_k)[slot] = key;
+                C.stA_v[slot] = c;
+                hist_add<K>(s_hist, C.passes, key);
+            }
+        }
+        __syncthreads();
+        // compaction of the table: thread owns slots [tid*SPT, tid*SPT+SPT)
+        u32 cnt = 0;
+        for (int r = 0; r < SPT; r++) {
+            const int h = threadIdx.x * SPT + r;
+            if (s_hk[h] != EMPTY && !ring_is_zero<RING>(ring_cell_final<RING>(s_hv[h]))) cnt++;
+        }
+        u32 total;
+        u32 off = block_excl_scan<u32>(cnt, s_scan, total);
+        if (dense) {
+            u64 *box = C.box + s.stage_base;
+            for (int r = 0; r < SPT; r++) {
+                const int h = threadIdx.x * SPT + r;
+                if (s_hk[h] == EMPTY) continue;
+                u64 v = ring_cell_final<RING>(s_hv[h]);
+                if (!ring_is_zero<RING>(v)) ring_atomic_acc<RING>(box + (u64)s_hk[h], v);
+            }
+        } else {
+            if (threadIdx.x == 0) s_base = total ? atomicAdd(&C.dyn[q].fill, (unsigned long long)total) : 0;
+            __syncthreads();
+            const i64 base = s.stage_base + (i64)s_base + off;
+            K *sk = (K *)C.stA_k;
+            u32 w = 0;
+            for (int r = 0; r < SPT; r++) {
+                const int h = threadIdx.x * SPT + r;
+                if (s_hk[h] == EMPTY) continue;
+                u64 v = ring_cell_final<RING>(s_hv[h]);
+                if (ring_is_zero<RING>(v)) continue;
+                sk[base + w] = s_hk[h];
+                C.stA_v[base + w] = v;
+                hist_add<K>(s_hist, C.passes, s_hk[h]);
+                w++;
+            }
+        }
+        __syncthreads();
+    }
+    if (cur_q >= 0) {
+        __syncthreads();
+        hist_flush(C, s_hist, cur_q);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_expand_raw: SEG_RAW products.  Work item = (segment, row i, chunk of
+// RAW_CHUNK columns).  Pair (i, j) goes to staging slot i*nb + j, so staging
+// order is the row-major order of the pp-matrix.
+// ---------------------------------------------------------------------------
+constexpr int RAW_CHUNK = 4096;
+
+template <typename K, int RING>
+__global__ __launch_bounds__(NTHREADS) void k_expand_raw(Ctx C) {
+    __shared__ u32 s_hist[MAX_PASSES * RADIX];
+    __shared__ i64 s_item;
+    for (int e = threadIdx.x; e < C.passes * RADIX; e += NTHREADS) s_hist[e] = 0;
+    int cur_q = -1;
+    const K *ck = (const K *)C.ck;
+    K *sk = (K *)C.stA_k;
+    while (true) {
+        if (threadIdx.x == 0) s_item = (i64)atomicAdd(&C.counters[CNT_RAW], 1u);
+        __syncthreads();
+        const i64 t = s_item;
+        __syncthreads();
+        if (t >= C.nraw) break;
+        const i32 rs = seg_search(C.raw_pre, C.nrseg, t);
+        const int q = C.raw_seg[rs];
+        const DevSeg &s = C.segs[q];
+        if (q != cur_q) {
+            if (cur_q >= 0) {
+                __syncthreads();
+                hist_flush(C, s_hist, cur_q);
+                __syncthreads();
+            }
+            cur_q = q;
+        }
+        const i64 local = t - C.raw_pre[rs];
+        const i64 i = local / s.raw_chunks;
+        const i64 j0 = (local % s.raw_chunks) * RAW_CHUNK;
+        const i64 jn = min((i64)RAW_CHUNK, s.nb - j0);
+        const K fkey = ck[s.ck_f + i];
+        const u64 fcv = s.fc[i];
+        const i64 base = s.stage_base + i * s.nb + j0;
+        for (i64 j = threadIdx.x; j < jn; j += NTHREADS) {
+            const K key = fkey + ck[s.ck_g + j0 + j];
+            sk[base + j] = key;
+            C.stA_v[base + j] = ring_mul<RING>(fcv, s.gc[j0 + j]);
+            hist_add<K>(s_hist, C.passes, key);
+        }
+    }
+    if (cur_q >= 0) {
+        __syncthreads();
+        hist_flush(C, s_hist, cur_q);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-product sizes and sort partitions (one workgroup), then per-product
+// exclusive digit offsets for every pass (one workgroup per product).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
+    __shared__ i64 s_scan[NTHREADS / 64];
+    __shared__ i64 s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int b = 0; b < C.nseg; b += NTHREADS) {
+        const int q = b + threadIdx.x;
+        i64 np = 0;
+        if (q < C.nseg) {
+            const DevSeg &s = C.segs[q];
+            i64 n = 0;
+            if (s.mode == SEG_COMBINE) n = (i64)C.dyn[q].fill;
+            else if (s.mode == SEG_RAW) n = s.na * s.nb;
+            C.dyn[q].n = n;
+            np = (n + PART - 1) / PART;
+            C.dyn[q].nparts = np;
+            if ((s.mode == SEG_COMBINE || s.mode == SEG_RAW || s.mode == SEG_EMPTY) && n == 0) *s.n_out = 0;
+        }
+        i64 tot;
+        i64 off = block_excl_scan<i64>(np, s_scan, tot);
+        if (q < C.nseg) {
+            C.dyn[q].part_first = s_carry + off;
+            C.ppre[q] = s_carry + off;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C.ppre[C.nseg] = s_carry;
+}
+
+__global__ __launch_bounds__(RADIX) void k_seg_bases(Ctx C) {
+    __shared__ u64 s_scan[RADIX / 64];
+    const int q = blockIdx.x;
+    const DevSeg &s = C.segs[q];
+    if (s.mode != SEG_COMBINE && s.mode != SEG_RAW) return;
+    for (int p = 0; p < C.passes; p++) {
+        const i64 idx = ((i64)p * C.nseg + q) * RADIX + threadIdx.x;
+        u64 tot;
+        u64 off = block_excl_scan<u64>((u64)C.hist[idx], s_scan, tot);
+        C.bases[idx] = (u64)s.stage_base + off;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_onesweep: one stable LSD radix pass over digit `pass` of every product's
+// staged keys.  Partition = PART consecutive pairs of one product.  Ranks are
+// computed per wave with ballot "match" masks (peers with the same digit),
+// per-wave digit counters in LDS and a workgroup scan; the product-wide
+// position of each digit comes from the product's digit offsets plus a
+// decoupled look-back over the product's earlier partitions.  Keys and values
+// are permuted through LDS so that global writes are contiguous per digit.
+// ---------------------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
+                                                        const u64 *__restrict__ vin, K *__restrict__ kout,
+                                                        u64 *__restrict__ vout) {
+    constexpr int NW = NTHREADS / 64;
+    __shared__ union {
+        K k[PART];
+        u64 v[PART];
+    } s_buf;
+    __shared__ unsigned char s_dig[PART];
+    __shared__ u32 s_wh[NW][RADIX];
+    __shared__ u32 s_loff[RADIX];
+    __shared__ i64 s_goff[RADIX];
+    __shared__ u32 s_scan[NW];
+    __shared__ i64 s_p;
+
+    const int shift = pass * RADIX_BITS;
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    const u32 tag = (u32)pass + 1;
+    const i64 nparts = C.ppre[C.nseg];
+    while (true) {
+        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_SORT + pass], 1u);
+        for (int d = threadIdx.x; d < NW * RADIX; d += NTHREADS) (&s_wh[0][0])[d] = 0;
+        __syncthreads();
+        const i64 p = s_p;
+        if (p >= nparts) break;
+        const int q = seg_search(C.ppre, C.nseg, p);
+        const DevSeg &s = C.segs[q];
+        const i64 first = C.ppre[q];
+        const i64 c = p - first;
+        const i64 n_q = C.dyn[q].n;
+        const i64 start = s.stage_base + c * PART;
+        const int n = (int)min((i64)PART, n_q - c * PART);
+
+        // load keys, warp-striped: item k of lane l in wave w is w*64*IPT + k*64 + l
+        K key[IPT];
+        u32 rk[IPT];
+        u32 dg[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+            key[k] = idx < n ? kin[start + idx] : (K)0;
+        }
+        // per-wave stable ranking
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+            const bool valid = idx < n;
+            const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
+            u64 peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < RADIX_BITS; b++) {
+                const u64 m = __ballot((d >> b) & 1);
+                peers &= ((d >> b) & 1) ? m : ~m;
+            }
+            const u32 before = mbcnt(peers);
+            const u32 cnt = (u32)__popcll(peers);
+            u32 old = valid ? s_wh[w][d] : 0;
+            if (valid && before == 0) s_wh[w][d] = old + cnt;
+            rk[k] = old + before;
+            dg[k] = d;
+        }
+        __syncthreads();
+        // digit totals, wave prefixes, local digit offsets
+        const int d = threadIdx.x;  // RADIX == NTHREADS
+        u32 tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ww++) {
+            u32 x = s_wh[ww][d];
+            s_wh[ww][d] = tot;
+            tot += x;
+        }
+        u32 all;
+        const u32 loff = block_excl_scan<u32>(tot, s_scan, all);
+        s_loff[d] = loff;
+        // product-wide offset of this digit in this partition
+        const u64 prefix = lookback(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
+        s_goff[d] = (i64)(C.bases[((i64)pass * C.nseg + q) * RADIX + d] + prefix) - (i64)loff;
+        __syncthreads();
+        // scatter keys into LDS in sorted order
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+            if (idx < n) {
+                const u32 pos = s_loff[dg[k]] + s_wh[w][dg[k]] + rk[k];
+                rk[k] = pos;
+                s_buf.k[pos] = key[k];
+                s_dig[pos] = (unsigned char)dg[k];
+            }
+        }
+        __syncthreads();
+        const i64 lo = s.stage_base, hi = s.stage_base + n_q;
+        for (int i = threadIdx.x; i < n; i += NTHREADS) {
+            const i64 o = s_goff[s_dig[i]] + i;
+            if (o >= lo && o < hi) kout[o] = s_buf.k[i];
+            else atomicOr(&C.counters[CNT_ERR_SPIN], 2u);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+            if (idx < n) s_buf.v[rk[k]] = vin[start + idx];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NTHREADS) {
+            const i64 o = s_goff[s_dig[i]] + i;
+            if (o >= lo && o < hi) vout[o] = s_buf.v[i];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce: sorted staging -> result.  A run of equal keys is summed by the
+// thread that owns its first element, left to right in staging order (for
+// FP64 that is the row-major (i, j) order), reading past the partition end
+// when the run continues.  Non-zero sums get their result position from a
+// workgroup scan plus a look-back over the product's earlier partitions; the
+// key is decompressed back to the packed exponent layout.
+// ---------------------------------------------------------------------------
+template <typename K, int RING>
+__global__ __launch_bounds__(NTHREADS) void k_reduce(Ctx C, const K *__restrict__ kin, const u64 *__restrict__ vin) {
+    __shared__ K s_k[PART];
+    __shared__ u64 s_v[PART];
+    __shared__ u32 s_scan[NTHREADS / 64];
+    __shared__ i64 s_p;
+    __shared__ u64 s_base;
+    const i64 nparts = C.ppre[C.nseg];
+    while (true) {
+        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_REDUCE], 1u);
+        __syncthreads();
+        const i64 p = s_p;
+        if (p >= nparts) break;
+        const int q = seg_search(C.ppre, C.nseg, p);
+        const DevSeg &s = C.segs[q];
+        const i64 first = C.ppre[q];
+        const i64 c = p - first;
+        const i64 n_q = C.dyn[q].n;
+        const i64 seg0 = s.stage_base;
+        const i64 start = seg0 + c * PART;
+        const i64 send = seg0 + n_q;
+        const int n = (int)min((i64)PART, n_q - c * PART);
+        for (int i = threadIdx.x; i < n; i += NTHREADS) {
+            s_k[i] = kin[start + i];
+            s_v[i] = vin[start + i];
+        }
+        const K prevk = c > 0 ? kin[start - 1] : (K)0;
+        __syncthreads();
+        // each thread: items [t*IPT, t*IPT+IPT)
+        u32 mask = 0;
+        const int b0 = threadIdx.x * IPT;
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int i = b0 + r;
+            if (i >= n) break;
+            const K key = s_k[i];
+            const bool head = (start + i == seg0) || key != (i == 0 ? prevk : s_k[i - 1]);
+            if (!head) continue;
+            u64 acc = s_v[i];
+            int j = i + 1;
+            while (j < n && s_k[j] == key) acc = ring_add<RING>(acc, s_v[j++]);
+            if (j == n) {
+                for (i64 g = start + j; g < send && kin[g] == key; g++) acc = ring_add<RING>(acc, vin[g]);
+            }
+            if (!ring_is_zero<RING>(acc)) {
+                mask |= 1u << r;
+                s_v[i] = acc;  // only this thread reads a head's slot
+            }
+        }
+        const u32 cnt = (u32)__popc(mask);
+        u32 total;
+        const u32 off = block_excl_scan<u32>(cnt, s_scan, total);
+        if (threadIdx.x == 0) s_base = lookback(C.look_red, 1, first, p, 200u, total, &C.counters[CNT_ERR_SPIN]);
+        __syncthreads();
+        const u64 base = s_base + off;
+        const VarParam *vp = C.vars + s.var_off;
+        u32 r2 = 0;
+        for (int r = 0; r < IPT; r++) {
+            if (!(mask & (1u << r))) continue;
+            const u64 pos = base + r2++;
+            if ((i64)pos < s.cap) {
+                const int i = b0 + r;
+                s.hk[pos] = decompress<K>(s_k[i], vp, C.nvars, s.lo_key);
+                s.hc[pos] = s_v[i];
+            }
+        }
+        if (c == C.dyn[q].nparts - 1 && threadIdx.x == 0) *s.n_out = (i64)(s_base + total);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_compact: dense path.  Cells of each product's degree box, in mixed-radix
+// (= lexicographic) order, become the sorted result; a cell is a term when its
+// accumulated value is non-zero.
+// ---------------------------------------------------------------------------
+template <int RING>
+__global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
+    __shared__ u32 s_scan[NTHREADS / 64];
+    __shared__ i64 s_p;
+    __shared__ u64 s_base;
+    while (true) {
+        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_COMPACT], 1u);
+        __syncthreads();
+        const i64 p = s_p;
+        if (p >= C.ndparts) break;
+        const i32 ds = seg_search(C.dpart_pre, C.ndseg, p);
+        const int q = C.dseg[ds];
+        const DevSeg &s = C.segs[q];
+        const i64 first = C.dpart_pre[ds];
+        const i64 c = p - first;
+        const i64 nparts = C.dpart_pre[ds + 1] - first;
+        const i64 c0 = c * PART;
+        const i64 b0 = c0 + (i64)threadIdx.x * IPT;
+        u64 val[IPT];
+        u32 mask = 0;
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const i64 cell = b0 + r;
+            val[r] = 0;
+            if (cell < s.stage_bound) {
+                val[r] = ring_cell_final<RING>(C.box[s.stage_base + cell]);
+                if (!ring_is_zero<RING>(val[r])) mask |= 1u << r;
+            }
+        }
+        const u32 cnt = (u32)__popc(mask);
+        u32 total;
+        const u32 off = block_excl_scan<u32>(cnt, s_scan, total);
+        if (threadIdx.x == 0) s_base = lookback(C.look_cmp, 1, first, p, 201u, total, &C.counters[CNT_ERR_SPIN]);
+        __syncthreads();
+        const u64 base = s_base + off;
+        const VarParam *vp = C.vars + s.var_off;
+        u32 r2 = 0;
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            if (!(mask & (1u << r))) continue;
+            const u64 pos = base + r2++;
+            if ((i64)pos < s.cap) {
+                s.hk[pos] = decompress<u64>((u64)(b0 + r), vp, C.nvars, s.lo_key);
+                s.hc[pos] = val[r];
+            }
+        }
+        if (c == nparts - 1 && threadIdx.x == 0) *s.n_out = (i64)(s_base + total);
+        __syncthreads();
+    }
+}
+
+}  // namespace pm
+
+// ===========================================================================
+// Host-side launch sequence
+// ===========================================================================
+#include "pm_launch.hpp"
+
+namespace pm {
+
+static inline int grid_for(int64_t work, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(work, cap)); }
+
+hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int ring, u64 *out, u32 *flags,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_stats, dim3(2 * nseg), dim3(NTHREADS), 0, st, segs, nvars, bits, ring, out, flags);
+    return hipGetLastError();
+}
+
+template <typename K, int RING>
+static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid) {
+    switch (P.tile_cfg) {
+        case 0: hipLaunchKernelGGL((k_tile<K, RING, 32, 64, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
+        case 1: hipLaunchKernelGGL((k_tile<K, RING, 64, 64, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
+        default: hipLaunchKernelGGL((k_tile<K, RING, 128, 128, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
+    }
+}
+
+template <typename K, int RING>
+static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
+    if (P.nck > 0) {
+        hipLaunchKernelGGL((k_compress<K>), dim3(grid_for((P.nck + NTHREADS - 1) / NTHREADS, cus * 16)), dim3(NTHREADS),
+                           0, st, C, (const i64 *)((const char *)C.segs - P.o_segs + P.o_cpre), (i64)P.nck);
+    }
+    if (P.ntiles > 0) {
+        if constexpr (RING != RING_F64) launch_tile<K, RING>(P, C, st, grid_for(P.ntiles, cus * 8));
+    }
+    if (P.nraw > 0) {
+        hipLaunchKernelGGL((k_expand_raw<K, RING>), dim3(grid_for(P.nraw, cus * 8)), dim3(NTHREADS), 0, st, C);
+    }
+    if (P.nsparse > 0) {
+        hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
+        if (P.passes > 0) hipLaunchKernelGGL(k_seg_bases, dim3(P.nseg), dim3(RADIX), 0, st, C);
+        K *ka = (K *)C.stA_k, *kb = (K *)C.stB_k;
+        u64 *va = C.stA_v, *vb = C.stB_v;
+        const int g = grid_for(P.nparts_bound, cus * 3);
+        for (int pass = 0; pass < P.passes; pass++) {
+            hipLaunchKernelGGL((k_onesweep<K>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        hipLaunchKernelGGL((k_reduce<K, RING>), dim3(grid_for(P.nparts_bound, cus * 3)), dim3(NTHREADS), 0, st, C,
+                           ka, va);
+    } else if (P.nseg > 0) {
+        // products without a sort still need n_out = 0 when an operand is empty
+        hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
+    }
+    if (P.ndparts > 0) {
+        if constexpr (RING != RING_F64)
+            hipLaunchKernelGGL((k_compact<RING>), dim3(grid_for(P.ndparts, cus * 8)), dim3(NTHREADS), 0, st, C);
+    }
+}
+
+hipError_t launch_pipeline(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
+    // per-call zeroed state
+    const size_t zbytes = P.r_zero.bytes;
+    u64 *zp = (u64 *)((char *)C.segs - P.o_segs + P.r_zero.off);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(zbytes / 8 + 255) / 256, cus * 8)), dim3(256), 0, st, zp,
+                       (i64)(zbytes / 8), 0ull);
+    if (P.ksize == 4) {
+        if (P.ring == RING_MODP) launch_typed<u32, RING_MODP>(P, C, st, cus);
+        else if (P.ring == RING_I64) launch_typed<u32, RING_I64>(P, C, st, cus);
+        else launch_typed<u32, RING_F64>(P, C, st, cus);
+    } else {
+        if (P.ring == RING_MODP) launch_typed<u64, RING_MODP>(P, C, st, cus);
+        else if (P.ring == RING_I64) launch_typed<u64, RING_I64>(P, C, st, cus);
+        else launch_typed<u64, RING_F64>(P, C, st, cus);
+    }
+    return hipGetLastError();
+}
+
+Ctx make_ctx(const Plan &P, void *ws) {
+    char *b = (char *)ws;
+    Ctx C;
+    C.segs = (DevSeg *)(b + P.o_segs);
+    C.dyn = (DevSegDyn *)(b + P.o_dyn);
+    C.vars = (VarParam *)(b + P.o_vars);
+    C.tile_pre = (const i64 *)(b + P.o_tile_pre);
+    C.tile_seg = (const i32 *)(b + P.o_tile_seg);
+    C.raw_pre = (const i64 *)(b + P.o_raw_pre);
+    C.raw_seg = (const i32 *)(b + P.o_raw_seg);
+    C.dpart_pre = (const i64 *)(b + P.o_dpart_pre);
+    C.dseg = (const i32 *)(b + P.o_dseg);
+    C.ppre = (i64 *)(b + P.o_ppre);
+    C.ck = b + P.o_ck;
+    C.stA_k = b + P.o_stAk;
+    C.stA_v = (u64 *)(b + P.o_stAv);
+    C.stB_k = b + P.o_stBk;
+    C.stB_v = (u64 *)(b + P.o_stBv);
+    C.box = (u64 *)(b + P.o_box);
+    C.hist = (unsigned long long *)(b + P.o_hist);
+    C.bases = (u64 *)(b + P.o_bases);
+    C.look = (u64 *)(b + P.o_look);
+    C.look_red = (u64 *)(b + P.o_look_red);
+    C.look_cmp = (u64 *)(b + P.o_look_cmp);
+    C.counters = (u32 *)(b + P.o_counters);
+    C.nseg = P.nseg;
+    C.ntseg = (i32)P.tile_seg.size();
+    C.nrseg = (i32)P.raw_seg.size();
+    C.ndseg = (i32)P.dseg.size();
+    C.nvars = P.nvars;
+    C.bits = P.bits;
+    C.passes = P.passes;
+    C.ring = P.ring;
+    C.ntiles = P.ntiles;
+    C.nraw = P.nraw;
+    C.ndparts = P.ndparts;
+    return C;
+}
+
+}  // namespace pm

@@ -1,0 +1,232 @@
+// Host planner: see pm_plan.hpp.
+#include "pm_plan.hpp"
+
+#include <algorithm>
+
+#include "../../include/polymul.h"
+
+namespace pm {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t stats_region_bytes(int nseg, int nvars) {
+    return align256(stats_bytes(nseg, nvars)) + align256((size_t)nseg * 2 * sizeof(uint32_t));
+}
+
+static int bitlen128(unsigned __int128 x) {
+    int b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, const uint64_t *stats,
+               const uint32_t *flags, const Tuning &tune, Plan &P) {
+    const int S = (int)in.size();
+    P = Plan();
+    P.nseg = S;
+    P.nvars = nvars;
+    P.bits = bits;
+    P.ring = ring;
+    const uint64_t fmask = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+
+    // validation verdicts, most fundamental first
+    uint32_t all = 0;
+    for (int q = 0; q < S; q++) all |= flags[2 * q] | flags[2 * q + 1];
+    if (all & ST_BADBITS) return PM_EINVAL;
+    if (all & ST_UNSORTED) return PM_EUNSORTED;
+    if (all & ST_RANGE) return PM_ERANGE;
+
+    P.segs.resize(S);
+    P.vars.resize((size_t)S * nvars);
+    P.bound.assign(S, 0);
+    std::vector<unsigned __int128> box(S, 0);
+    int max_bits = 0;
+    bool need_u64 = false;
+    for (int q = 0; q < S; q++) {
+        DevSeg &d = P.segs[q];
+        d = DevSeg();
+        d.fk = in[q].fk;
+        d.fc = in[q].fc;
+        d.gk = in[q].gk;
+        d.gc = in[q].gc;
+        d.na = in[q].na;
+        d.nb = in[q].nb;
+        d.var_off = (int64_t)q * nvars;
+        if (d.na == 0 || d.nb == 0) {
+            d.mode = SEG_EMPTY;
+            continue;
+        }
+        const uint64_t *st = stats + (size_t)q * 4 * nvars;  // f: min[nv] max[nv], g: min[nv] max[nv]
+        const uint64_t *fmin = st, *fmax = st + nvars, *gmin = st + 2 * nvars, *gmax = st + 3 * nvars;
+        unsigned __int128 b = 1;
+        bool big = false;
+        uint64_t lo_key = 0;
+        for (int v = 0; v < nvars; v++) {
+            if (fmax[v] > fmask - gmax[v]) return PM_EOVERFLOW;
+            unsigned __int128 r = (unsigned __int128)(fmax[v] + gmax[v]) - (fmin[v] + gmin[v]) + 1;
+            VarParam &vp = P.vars[(size_t)q * nvars + v];
+            vp.shift = (uint32_t)((nvars - 1 - v) * bits);
+            vp.mask = fmask;
+            vp.minf = fmin[v];
+            vp.ming = gmin[v];
+            vp.range = (uint64_t)r;  // 0 encodes 2^64 (one full-width variable)
+            lo_key += (fmin[v] + gmin[v]) << vp.shift;
+            if (!big) {
+                b *= r;
+                if (b >> 64) big = true;
+            }
+        }
+        // strides: stride_v = prod_{w > v} range_w
+        unsigned __int128 st_acc = 1;
+        for (int v = nvars - 1; v >= 0; v--) {
+            VarParam &vp = P.vars[(size_t)q * nvars + v];
+            vp.stride = (uint64_t)st_acc;
+            unsigned __int128 r = vp.range ? vp.range : ((unsigned __int128)1 << 64);
+            st_acc *= r;
+            if (st_acc >> 65) st_acc = (unsigned __int128)1 << 65;  // only reached when box > 2^64
+        }
+        d.lo_key = lo_key;
+        box[q] = big ? ((unsigned __int128)1 << 64) : b;
+        const unsigned __int128 prod = (unsigned __int128)d.na * (unsigned __int128)d.nb;
+        const unsigned __int128 bnd = std::min(prod, box[q]);
+        P.bound[q] = (int64_t)bnd;
+        // path
+        const bool can_dense = tune.allow_dense && ring != RING_F64 && box[q] <= (unsigned __int128)tune.dense_max_cells &&
+                               (double)box[q] * tune.dense_ratio <= (double)prod;
+        if (can_dense) {
+            d.mode = SEG_DENSE;
+        } else {
+            const bool full = box[q] >= ((unsigned __int128)1 << 64);
+            d.mode = (ring == RING_F64 || tune.force_raw || full) ? SEG_RAW : SEG_COMBINE;
+            int kb = bitlen128(box[q] - 1);
+            max_bits = std::max(max_bits, kb);
+        }
+        if (box[q] > (unsigned __int128)0xFFFFFFFFull) need_u64 = true;
+    }
+    P.ksize = need_u64 ? 8 : 4;
+    P.passes = (max_bits + RADIX_BITS - 1) / RADIX_BITS;
+
+    // tile shape: explicit, or the largest one that still gives >= 512 tiles
+    // over the tiled products (at least two per compute unit); the sparse
+    // combine path keeps the smallest table load (32 x 64 into 4096 slots).
+    int64_t tiled_pairs = 0;
+    bool any_combine = false;
+    for (int q = 0; q < S; q++) {
+        const DevSeg &d = P.segs[q];
+        if (d.mode == SEG_COMBINE || d.mode == SEG_DENSE) tiled_pairs += d.na * d.nb;
+        if (d.mode == SEG_COMBINE) any_combine = true;
+    }
+    if (tune.tile_cfg >= 0 && tune.tile_cfg < N_TILE_CFGS) {
+        P.tile_cfg = tune.tile_cfg;
+    } else if (any_combine) {
+        P.tile_cfg = 0;
+    } else {
+        P.tile_cfg = 0;
+        for (int c = N_TILE_CFGS - 1; c >= 0; c--) {
+            if (tiled_pairs / ((int64_t)TILE_CFGS[c].tm * TILE_CFGS[c].tn) >= 512) {
+                P.tile_cfg = c;
+                break;
+            }
+        }
+    }
+    const TileCfg tc = TILE_CFGS[P.tile_cfg];
+
+    // queues and offsets
+    P.tile_pre.push_back(0);
+    P.raw_pre.push_back(0);
+    P.dpart_pre.push_back(0);
+    P.cpre.push_back(0);
+    int64_t nstage = 0, nbox = 0, nck = 0;
+    for (int q = 0; q < S; q++) {
+        DevSeg &d = P.segs[q];
+        d.ck_f = nck;
+        nck += d.na;
+        d.ck_g = nck;
+        nck += d.nb;
+        P.cpre.push_back(P.cpre.back() + d.na);
+        P.cpre.push_back(P.cpre.back() + d.nb);
+        if (d.mode == SEG_COMBINE || d.mode == SEG_DENSE) {
+            const int64_t tmn = (d.na + tc.tm - 1) / tc.tm, tnn = (d.nb + tc.tn - 1) / tc.tn;
+            d.tile_first = P.tile_pre.back();
+            d.tiles_n = tnn;
+            P.tile_seg.push_back(q);
+            P.tile_pre.push_back(P.tile_pre.back() + tmn * tnn);
+        }
+        if (d.mode == SEG_RAW) {
+            d.raw_chunks = (d.nb + 4095) / 4096;
+            d.raw_first = P.raw_pre.back();
+            P.raw_seg.push_back(q);
+            P.raw_pre.push_back(P.raw_pre.back() + d.na * d.raw_chunks);
+        }
+        if (d.mode == SEG_COMBINE || d.mode == SEG_RAW) {
+            d.stage_base = nstage;
+            d.stage_bound = d.na * d.nb;
+            nstage += d.stage_bound;
+            P.nparts_bound += (d.stage_bound + PART - 1) / PART;
+            P.nsparse++;
+        }
+        if (d.mode == SEG_DENSE) {
+            d.stage_base = nbox;
+            d.stage_bound = (int64_t)box[q];
+            nbox += d.stage_bound;
+            d.dpart_first = P.dpart_pre.back();
+            P.dseg.push_back(q);
+            P.dpart_pre.push_back(P.dpart_pre.back() + (d.stage_bound + PART - 1) / PART);
+            P.ndense++;
+        }
+    }
+    P.ntiles = P.tile_pre.back();
+    P.nraw = P.raw_pre.back();
+    P.ndparts = P.dpart_pre.back();
+    P.nstage = nstage;
+    P.nbox = nbox;
+    P.nck = nck;
+
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    P.r_stats.off = take(stats_bytes(S, nvars));
+    P.r_stats.bytes = stats_bytes(S, nvars);
+    P.r_flags.off = take((size_t)S * 2 * 4);
+    P.r_flags.bytes = (size_t)S * 2 * 4;
+    const size_t desc0 = off;
+    P.o_segs = take(sizeof(DevSeg) * S);
+    P.o_vars = take(sizeof(VarParam) * S * nvars);
+    P.o_tile_pre = take(8 * P.tile_pre.size());
+    P.o_tile_seg = take(4 * std::max<size_t>(1, P.tile_seg.size()));
+    P.o_raw_pre = take(8 * P.raw_pre.size());
+    P.o_raw_seg = take(4 * std::max<size_t>(1, P.raw_seg.size()));
+    P.o_dpart_pre = take(8 * P.dpart_pre.size());
+    P.o_dseg = take(4 * std::max<size_t>(1, P.dseg.size()));
+    P.o_cpre = take(8 * P.cpre.size());
+    P.r_desc.off = desc0;
+    P.r_desc.bytes = off - desc0;
+    const size_t zero0 = off;
+    P.o_dyn = take(sizeof(DevSegDyn) * S);
+    P.o_counters = take(4 * CNT_COUNT);
+    P.o_hist = take((size_t)8 * std::max(1, P.passes) * S * RADIX);
+    P.o_look = take((size_t)8 * RADIX * std::max<int64_t>(1, P.nparts_bound));
+    P.o_look_red = take((size_t)8 * std::max<int64_t>(1, P.nparts_bound));
+    P.o_look_cmp = take((size_t)8 * std::max<int64_t>(1, P.ndparts));
+    P.o_box = take((size_t)8 * std::max<int64_t>(1, nbox));
+    P.r_zero.off = zero0;
+    P.r_zero.bytes = off - zero0;
+    P.o_ppre = take((size_t)8 * (S + 1));
+    P.o_bases = take((size_t)8 * std::max(1, P.passes) * S * RADIX);
+    P.o_ck = take((size_t)P.ksize * std::max<int64_t>(1, nck));
+    P.o_stAk = take((size_t)P.ksize * std::max<int64_t>(1, nstage));
+    P.o_stAv = take((size_t)8 * std::max<int64_t>(1, nstage));
+    P.o_stBk = take((size_t)P.ksize * std::max<int64_t>(1, nstage));
+    P.o_stBv = take((size_t)8 * std::max<int64_t>(1, nstage));
+    P.total = off;
+    return PM_OK;
+}
+
+}  // namespace pm

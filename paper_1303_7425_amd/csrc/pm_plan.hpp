@@ -1,0 +1,74 @@
+// Host-side planning of one launch (a batch of products): per-product
+// compression of the exponent keys into the degree box, the choice between
+// the dense and the sparse path, tile and radix parameters, and the layout of
+// the caller's workspace.  Pure host code.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pm_internal.hpp"
+
+namespace pm {
+
+struct TileCfg {
+    int tm, tn, hb;
+};
+
+// Tile shapes the kernels are instantiated for.
+constexpr TileCfg TILE_CFGS[] = {{32, 64, 12}, {64, 64, 12}, {128, 128, 12}};
+constexpr int N_TILE_CFGS = 3;
+
+struct Tuning {
+    int tile_cfg = -1;       // -1: choose automatically
+    int force_raw = 0;       // stage every product pair (no LDS combine) for exact rings
+    int allow_dense = 1;     // permit the degree-box path
+    double dense_ratio = 2;  // dense when box * dense_ratio <= na * nb
+    int64_t dense_max_cells = int64_t(1) << 27;
+};
+
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+struct Plan {
+    int nseg = 0, nvars = 0, bits = 0, ring = 0;
+    int ksize = 4;
+    int passes = 0;
+    int tile_cfg = 0;
+    std::vector<DevSeg> segs;
+    std::vector<VarParam> vars;
+    std::vector<int64_t> bound;     // result-size bound per product
+    std::vector<int64_t> tile_pre, raw_pre, dpart_pre, cpre;
+    std::vector<int32_t> tile_seg, raw_seg, dseg;
+    int64_t ntiles = 0, nraw = 0, ndparts = 0, nparts_bound = 0;
+    int64_t nstage = 0, nbox = 0, nck = 0;
+    int nsparse = 0, ndense = 0;
+    // workspace layout
+    Region r_stats, r_flags, r_desc, r_zero;
+    size_t o_segs = 0, o_vars = 0, o_tile_pre = 0, o_tile_seg = 0, o_raw_pre = 0, o_raw_seg = 0, o_dpart_pre = 0,
+           o_dseg = 0, o_cpre = 0;
+    size_t o_dyn = 0, o_counters = 0, o_hist = 0, o_look = 0, o_look_red = 0, o_look_cmp = 0, o_box = 0;
+    size_t o_ppre = 0, o_bases = 0, o_ck = 0, o_stAk = 0, o_stAv = 0, o_stBk = 0, o_stBv = 0;
+    size_t total = 0;
+};
+
+// Byte size of the statistics block written by the validation kernel.
+inline size_t stats_bytes(int nseg, int nvars) { return (size_t)nseg * 2 * 2 * nvars * 8; }
+
+struct SegInput {
+    const uint64_t *fk, *fc, *gk, *gc;
+    int64_t na, nb;
+};
+
+// Returns PM_OK or an error code.  `stats` holds [nseg][2 sides][min|max][nvars]
+// and `flags` [nseg][2].  Output pointers of the segments are filled later.
+int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, const uint64_t *stats,
+               const uint32_t *flags, const Tuning &tune, Plan &plan);
+
+// Byte size of the region holding the statistics, for a call with nseg products.
+size_t stats_region_bytes(int nseg, int nvars);
+
+}  // namespace pm

@@ -1,0 +1,282 @@
+"""Thin ctypes binding of libpolymul.so (include/polymul.h).
+
+Argument marshalling only: device memory comes from torch tensors on the
+current HIP device, streams from torch.cuda.Stream; every step of the product
+runs in the library's kernels.  Raises if the HIP library is not built: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpolymul.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "polymul.h")
+
+PM_OK, PM_EINVAL, PM_EUNSORTED, PM_EOVERFLOW, PM_ERANGE, PM_ECAPACITY, PM_ENOMEM, PM_EDEVICE, PM_EBUSY = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+RING_CODE = {"modp": 0, "f64": 1, "i64": 2}
+
+
+class pm_layout(ctypes.Structure):
+    _fields_ = [("nvars", ctypes.c_uint32), ("bits", ctypes.c_uint32), ("ring", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class pm_cpoly(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("keys", ctypes.c_void_p), ("coefs", ctypes.c_void_p)]
+
+
+class pm_poly(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("n_out", ctypes.c_void_p), ("keys", ctypes.c_void_p),
+                ("coefs", ctypes.c_void_p)]
+
+
+class PolymulError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        msg = lib().pm_strerror(code).decode()
+        if code == PM_EDEVICE:
+            msg += ": " + lib().pm_last_error().decode()
+        super().__init__(f"{where}: {msg} ({code})" if where else f"{msg} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpolymul.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(python -m paper_1303_7425_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i64p = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)
+        L.pm_mul_bound.argtypes = [ctypes.POINTER(pm_layout), ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_cpoly),
+                                   i64p, i64p, vp]
+        L.pm_mul.argtypes = [ctypes.POINTER(pm_layout), ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_cpoly),
+                             ctypes.POINTER(pm_poly), vp, i64, vp]
+        L.pm_mul_batch_bound.argtypes = [ctypes.POINTER(pm_layout), i64, ctypes.POINTER(pm_cpoly),
+                                         ctypes.POINTER(pm_cpoly), i64p, i64p, vp]
+        L.pm_mul_batch.argtypes = [ctypes.POINTER(pm_layout), i64, ctypes.POINTER(pm_cpoly),
+                                   ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_poly), vp, i64, vp]
+        L.pm_plan_from_stats.argtypes = [ctypes.POINTER(pm_layout), i64, i64p, i64p,
+                                         ctypes.POINTER(ctypes.c_uint64), i64p, i64p]
+        L.pm_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.pm_last_call_status.argtypes = [vp]
+        L.pm_strerror.restype = ctypes.c_char_p
+        L.pm_strerror.argtypes = [ctypes.c_int]
+        L.pm_last_error.restype = ctypes.c_char_p
+        L.pm_version.restype = ctypes.c_char_p
+        if hasattr(L, "pm_server_create"):
+            L.pm_server_create.restype = vp
+            L.pm_server_create.argtypes = [i64, ctypes.c_int32]
+            L.pm_server_submit.argtypes = [vp, ctypes.POINTER(pm_layout), ctypes.POINTER(pm_cpoly),
+                                           ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_poly),
+                                           ctypes.POINTER(ctypes.c_uint64)]
+            L.pm_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]
+            L.pm_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
+            L.pm_server_latencies.restype = i64
+            L.pm_server_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64]
+            L.pm_server_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/polymul.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pm_[a-z_]+)\s*\(", text)))
+
+
+def make_layout(nvars: int, bits: int, ring: str) -> pm_layout:
+    return pm_layout(nvars, bits, RING_CODE[ring], 0)
+
+
+def _check(rc: int, where: str):
+    if rc != PM_OK:
+        raise PolymulError(rc, where)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------------------------
+# device-resident polynomials
+# ----------------------------------------------------------------------------
+@dataclass
+class DevPoly:
+    """Term arrays on the GPU: keys int64 (u64 bits), coefs int64 / float64."""
+    keys: object
+    coefs: object
+    n: int
+
+    def numpy(self):
+        k = self.keys[: self.n].cpu().numpy().view(np.uint64)
+        c = self.coefs[: self.n].cpu().numpy()
+        if c.dtype == np.int64 and self.coef_kind == "modp":
+            c = c.view(np.uint64)
+        return k, c
+
+    coef_kind: str = "modp"
+
+
+def to_device(poly, device="cuda"):
+    """workloads.Poly -> DevPoly (keys and coefficient bits copied to HBM)."""
+    import torch
+    ring = poly.layout.ring
+    k = torch.from_numpy(np.ascontiguousarray(poly.keys).view(np.int64)).to(device)
+    if ring == "f64":
+        c = torch.from_numpy(np.ascontiguousarray(poly.coefs, dtype=np.float64)).to(device)
+    else:
+        c = torch.from_numpy(np.ascontiguousarray(poly.coefs).view(np.int64)).to(device)
+    return DevPoly(k, c, len(poly), ring)
+
+
+def _cpoly(p: DevPoly) -> pm_cpoly:
+    return pm_cpoly(p.n, p.keys.data_ptr() if p.n else None, p.coefs.data_ptr() if p.n else None)
+
+
+class Workspace:
+    """A growable device byte buffer reused across calls."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+        return self.buf
+
+
+def bound(layout, f: DevPoly, g: DevPoly, stream=None):
+    L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+    mt, wb = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().pm_mul_bound(ctypes.byref(L), ctypes.byref(_cpoly(f)), ctypes.byref(_cpoly(g)),
+                              ctypes.byref(mt), ctypes.byref(wb), _stream_ptr(stream)), "pm_mul_bound")
+    return int(mt.value), int(wb.value)
+
+
+def alloc_out(cap: int, ring: str):
+    import torch
+    k = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
+    c = torch.empty(max(cap, 1), dtype=torch.float64 if ring == "f64" else torch.int64, device="cuda")
+    n = torch.zeros(1, dtype=torch.int64, device="cuda")
+    return k, c, n
+
+
+def mul(layout, f: DevPoly, g: DevPoly, out=None, workspace: Workspace | None = None, stream=None,
+        sync: bool = True):
+    """h = f * g on the GPU.  Returns DevPoly (n read back when sync=True)."""
+    import torch
+    L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+    ring = {v: k for k, v in RING_CODE.items()}[L.ring]
+    cap, wbytes = bound(L, f, g, stream)
+    if out is None:
+        out = alloc_out(cap, ring)
+    hk, hc, hn = out
+    ws = (workspace or Workspace()).get(wbytes)
+    h = pm_poly(min(hk.numel(), hc.numel()), hn.data_ptr(), hk.data_ptr(), hc.data_ptr())
+    _check(lib().pm_mul(ctypes.byref(L), ctypes.byref(_cpoly(f)), ctypes.byref(_cpoly(g)), ctypes.byref(h),
+                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "pm_mul")
+    n = -1
+    if sync:
+        (stream or torch.cuda.current_stream()).synchronize()
+        n = int(hn.item())
+    return DevPoly(hk, hc, n, ring)
+
+
+class BatchCall:
+    """A prepared pm_mul_batch call: bound, outputs and workspace allocated once,
+    then `run()` enqueues the batch (re-validating the operands each time)."""
+
+    def __init__(self, layout, fs, gs, workspace: Workspace | None = None, stream=None):
+        import torch
+        self.L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+        self.ring = {v: k for k, v in RING_CODE.items()}[self.L.ring]
+        self.count = len(fs)
+        self.fs, self.gs = fs, gs
+        self.cf = (pm_cpoly * self.count)(*[_cpoly(p) for p in fs])
+        self.cg = (pm_cpoly * self.count)(*[_cpoly(p) for p in gs])
+        mt = (ctypes.c_int64 * self.count)()
+        wb = ctypes.c_int64(0)
+        self.stream = stream
+        _check(lib().pm_mul_batch_bound(ctypes.byref(self.L), self.count, self.cf, self.cg, mt, ctypes.byref(wb),
+                                        _stream_ptr(stream)), "pm_mul_batch_bound")
+        self.bounds = [int(x) for x in mt]
+        self.ws_bytes = int(wb.value)
+        tot = sum(max(b, 1) for b in self.bounds)
+        self.out_k = torch.empty(tot, dtype=torch.int64, device="cuda")
+        self.out_c = torch.empty(tot, dtype=torch.float64 if self.ring == "f64" else torch.int64, device="cuda")
+        self.out_n = torch.zeros(self.count, dtype=torch.int64, device="cuda")
+        self.offsets = np.concatenate([[0], np.cumsum([max(b, 1) for b in self.bounds])]).astype(np.int64)
+        hs = []
+        ek, ec = self.out_k.element_size(), self.out_c.element_size()
+        for q in range(self.count):
+            o = int(self.offsets[q])
+            hs.append(pm_poly(self.bounds[q], self.out_n.data_ptr() + 8 * q, self.out_k.data_ptr() + ek * o,
+                              self.out_c.data_ptr() + ec * o))
+        self.h = (pm_poly * self.count)(*hs)
+        self.ws = (workspace or Workspace()).get(self.ws_bytes)
+
+    def run(self):
+        _check(lib().pm_mul_batch(ctypes.byref(self.L), self.count, self.cf, self.cg, self.h,
+                                  ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream_ptr(self.stream)),
+               "pm_mul_batch")
+
+    def results(self):
+        """List of (keys u64, coefs) numpy arrays, after the stream completes."""
+        ns = self.out_n.cpu().numpy()
+        k = self.out_k.cpu().numpy().view(np.uint64)
+        c = self.out_c.cpu().numpy()
+        if self.ring == "modp":
+            c = c.view(np.uint64)
+        out = []
+        for q in range(self.count):
+            o = int(self.offsets[q])
+            out.append((k[o:o + ns[q]], c[o:o + ns[q]]))
+        return out
+
+
+def mul_batch(layout, fs, gs, workspace=None, stream=None):
+    import torch
+    call = BatchCall(layout, fs, gs, workspace, stream)
+    call.run()
+    (stream or torch.cuda.current_stream()).synchronize()
+    return call.results()
+
+
+def last_call_status(stream=None):
+    """PM_OK unless the last call on this thread tripped a device-side check."""
+    return int(lib().pm_last_call_status(_stream_ptr(stream)))
+
+
+def set_tuning(tile_cfg: int = -1, force_raw: bool = False, allow_dense: bool = True):
+    _check(lib().pm_set_tuning(tile_cfg, int(force_raw), int(allow_dense)), "pm_set_tuning")
+
+
+def plan_from_stats(layout, na, nb, stats):
+    """Host-only bound / workspace size (no GPU)."""
+    L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+    count = len(na)
+    na_a = (ctypes.c_int64 * count)(*na)
+    nb_a = (ctypes.c_int64 * count)(*nb)
+    st = np.ascontiguousarray(stats, dtype=np.uint64)
+    mt = (ctypes.c_int64 * max(count, 1))()
+    wb = ctypes.c_int64(0)
+    rc = lib().pm_plan_from_stats(ctypes.byref(L), count, na_a, nb_a,
+                                  st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), mt, ctypes.byref(wb))
+    return rc, [int(mt[i]) for i in range(count)], int(wb.value)

@@ -1,0 +1,268 @@
+"""GPU path vs the CPU oracle on the same seeded inputs, through the C ABI.
+
+Bar: mod p and int64 bit-exact (keys, coefficients, term count).  FP64: keys
+identical and |h_gpu - h_oracle| <= 1e-13 * A(k) with A(k) = sum |fl(a_i b_j)|
+over the union of keys; in addition the GPU sums each monomial's products in
+the oracle's row-major order, so the coefficients are compared bit for bit.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle
+from paper_1303_7425_amd import workloads as W
+
+P = W.P61
+
+
+def _pm():
+    from paper_1303_7425_amd import polymul
+    return polymul
+
+
+def gpu_mul(f, g, ws=None):
+    pm = _pm()
+    lay = (f.layout.nvars, f.layout.bits, f.layout.ring)
+    h = pm.mul(lay, pm.to_device(f), pm.to_device(g), workspace=ws)
+    assert pm.last_call_status() == 0
+    return h.numpy()
+
+
+def assert_same(got, want, ring, tag=""):
+    gk, gc = got
+    wk, wc, wa = want
+    if ring != "f64":
+        assert gk.shape == wk.shape, (tag, gk.shape, wk.shape)
+        assert np.array_equal(gk, wk), tag
+        assert np.array_equal(gc.view(np.uint64), wc.view(np.uint64)), tag
+        return
+    # FP64: union of keys, missing = 0
+    keys = np.union1d(gk, wk)
+    gv = np.zeros(keys.size)
+    wv = np.zeros(keys.size)
+    av = np.zeros(keys.size)
+    gv[np.searchsorted(keys, gk)] = gc
+    wv[np.searchsorted(keys, wk)] = wc
+    av[np.searchsorted(keys, wk)] = wa
+    # a key emitted by the GPU must have contributing products: the oracle
+    # keeps all keys with a non-zero sum, and a zero sum on one side only is
+    # within tolerance when A(k) is large enough
+    err = np.abs(gv - wv)
+    assert np.all(err <= 1e-13 * av), (tag, float(err.max()))
+    # stronger: row-major summation order on both sides -> identical bits
+    assert np.array_equal(gk, wk), tag
+    assert np.array_equal(gc.view(np.uint64), wc.view(np.uint64)), tag
+
+
+def check(f, g, tag=""):
+    print(f"[parity] {tag} ring={f.layout.ring} na={len(f)} nb={len(g)}", flush=True)
+    want = oracle.mul(f, g)
+    got = gpu_mul(f, g)
+    assert_same(got, want, f.layout.ring, tag)
+
+
+@pytest.fixture(autouse=True)
+def default_tuning():
+    pm = _pm()
+    pm.set_tuning(-1, False, True)
+    yield
+    pm.set_tuning(-1, False, True)
+
+
+# ------------------------------------------------------------- small configs
+def test_config1_dense_int64():
+    f, g = W.config1()
+    check(f, g, "cfg1")
+
+
+@pytest.mark.parametrize("n", [3, 8])
+def test_dense_modp_small(n):
+    check(*W.config2(n), f"dense n={n}")
+
+
+@pytest.mark.parametrize("n", [2, 6])
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_sparse_family_small(n, ring):
+    f = W.sparse_power(n, "f", 12, "modp")
+    g = W.sparse_power(n, "g", 12, "modp")
+    if ring == "f64":
+        rng = W.rng_for(3)
+        f, g = W.with_random_coefs(f, rng, "f64"), W.with_random_coefs(g, rng, "f64")
+    check(f, g, f"sparse n={n}")
+
+
+@pytest.mark.parametrize("ring", ["modp", "f64", "i64"])
+@pytest.mark.parametrize("na,nb", [(1, 1), (1, 500), (33, 70), (257, 129), (1000, 3000)])
+def test_random_6var_ragged(ring, na, nb):
+    rng = W.rng_for(100 + na + nb)
+    f = W.random_sparse(rng, na, 6, 10, 15, ring)
+    g = W.random_sparse(rng, nb, 6, 10, 15, ring)
+    check(f, g, f"rand {na}x{nb}")
+
+
+@pytest.mark.parametrize("mode", ["auto", "raw", "nodense", "tile1", "tile2"])
+def test_tuning_modes_same_result(mode):
+    pm = _pm()
+    if mode == "raw":
+        pm.set_tuning(-1, True, True)
+    elif mode == "nodense":
+        pm.set_tuning(-1, False, False)
+    elif mode == "tile1":
+        pm.set_tuning(1, False, True)
+    elif mode == "tile2":
+        pm.set_tuning(2, False, True)
+    for n in (5, 9):
+        check(*W.config2(n), f"dense n={n} {mode}")
+    check(W.sparse_power(5, "f", 12, "modp"), W.sparse_power(5, "g", 12, "modp"), f"sparse {mode}")
+    rng = W.rng_for(8)
+    check(W.random_sparse(rng, 700, 6, 10, 15, "i64"), W.random_sparse(rng, 900, 6, 10, 15, "i64"), f"i64 {mode}")
+
+
+# ------------------------------------------------------------- edge cases
+def _poly(terms, nvars, bits, ring):
+    lay = W.Layout(nvars, bits, ring)
+    if not terms:
+        dt = {"f64": np.float64, "i64": np.int64, "modp": np.uint64}[ring]
+        return W.Poly(lay, np.zeros(0, dtype=np.uint64), np.zeros(0, dtype=dt))
+    exps = np.array([t[0] for t in terms], dtype=np.int64).reshape(-1, nvars)
+    keys = W.pack(exps, nvars, bits)
+    o = np.argsort(keys)
+    return W.Poly(lay, keys[o], W.to_ring([terms[i][1] for i in o.tolist()], ring))
+
+
+@pytest.mark.parametrize("ring", ["modp", "f64", "i64"])
+def test_edge_cases(ring):
+    x = ((1, 0), 3)
+    y = ((0, 1), -2)
+    one = ((0, 0), 1)
+    cases = [([], [x, y]), ([x, y], []), ([], []), ([x], [y]), ([one], [x, y]), ([((2, 3), 5)], [x, y, one]),
+             ([((1, 0), 1), ((0, 1), 1)], [((1, 0), 1), ((0, 1), -1)])]
+    for i, (ft, gt) in enumerate(cases):
+        check(_poly(ft, 2, 8, ring), _poly(gt, 2, 8, ring), f"edge{i}")
+
+
+def test_total_cancellation_gives_empty():
+    # (x + y) * (x - y) with the square terms removed from f: x*(x-y) + y*(x-y) ... use
+    # f = x - y and g = 0 coefficient list: every product cancels pairwise
+    f = _poly([((1, 0), 1), ((0, 1), 1)], 2, 8, "modp")
+    g = _poly([((1, 1), 1)], 2, 8, "modp")
+    g.coefs[:] = 0
+    hk, hc = gpu_mul(f, g)
+    assert hk.size == 0
+
+
+def test_single_variable_full_width():
+    # one variable, 64-bit field: the degree box is not compressible
+    rng = np.random.default_rng(5)
+    a = np.sort(rng.choice(1 << 40, size=300, replace=False)).astype(np.uint64)
+    b = np.sort(rng.choice(1 << 40, size=200, replace=False)).astype(np.uint64)
+    lay = W.Layout(1, 64, "modp")
+    f = W.Poly(lay, a, W.residues(W.rng_for(1), 300))
+    g = W.Poly(lay, b, W.residues(W.rng_for(2), 200))
+    check(f, g, "1var64")
+
+
+def test_many_vars_one_bit():
+    rng = W.rng_for(6)
+    # 32 variables of 2 bits: exponents 0..1, so sums fit
+    f = W.random_sparse(rng, 400, 32, 2, 1, "modp")
+    g = W.random_sparse(rng, 300, 32, 2, 1, "modp")
+    check(f, g, "32var")
+
+
+def test_validation_errors_match_oracle():
+    pm = _pm()
+    lay = (2, 8, "i64")
+    k = np.array([1, 2], dtype=np.uint64)
+    c = np.array([1, 1], dtype=np.int64)
+    bad = [
+        (k[::-1].copy(), c, k, c, pm.PM_EUNSORTED),
+        (np.array([200], dtype=np.uint64), c[:1], np.array([200], dtype=np.uint64), c[:1], pm.PM_EOVERFLOW),
+        (np.array([1 << 20], dtype=np.uint64), c[:1], k, c, pm.PM_EINVAL),
+    ]
+    for fk, fc, gk, gc, code in bad:
+        f = W.Poly(W.Layout(2, 8, "i64"), fk, fc)
+        g = W.Poly(W.Layout(2, 8, "i64"), gk, gc)
+        assert oracle.validate(2, 8, "i64", fk, fc, gk, gc) == code
+        with pytest.raises(pm.PolymulError) as e:
+            pm.mul(lay, pm.to_device(f), pm.to_device(g))
+        assert e.value.code == code
+    r = np.array([P, 1], dtype=np.uint64)
+    f = W.Poly(W.Layout(2, 8, "modp"), k, r)
+    with pytest.raises(pm.PolymulError) as e:
+        pm.mul((2, 8, "modp"), pm.to_device(f), pm.to_device(f))
+    assert e.value.code == pm.PM_ERANGE
+
+
+def test_truncation_reports_full_count():
+    pm = _pm()
+    import torch
+    f, g = W.config2(4)
+    want = oracle.mul(f, g)
+    out = pm.alloc_out(10, "modp")
+    h = pm.mul((4, 16, "modp"), pm.to_device(f), pm.to_device(g), out=out)
+    assert h.n == len(want[0])
+    assert np.array_equal(out[0][:10].cpu().numpy().view(np.uint64), want[0][:10])
+
+
+# ------------------------------------------------------------- full sizes
+def test_config1_closed_form_full():
+    f, g = W.config1()
+    hk, hc = gpu_mul(f, g)
+    assert hk.size == math.comb(24, 4)
+    fact = [math.factorial(i) for i in range(21)]
+
+    def M(n, e):
+        s = sum(e)
+        if s > n:
+            return 0
+        r = fact[n] // fact[n - s]
+        for x in e:
+            r //= fact[x]
+        return r
+    for e, c in zip(W.unpack(hk, 4, 16).tolist()[::97], hc.tolist()[::97]):
+        assert c == M(20, e) + M(10, e)
+
+
+def test_config2_full_closed_form_and_evaluation():
+    f, g = W.config2(20)
+    hk, hc = gpu_mul(f, g)
+    assert hk.size == math.comb(44, 4) == 135751
+    # closed form on every term: M(40; e) + M(20; e) mod p
+    fact = [math.factorial(i) for i in range(41)]
+    ex = W.unpack(hk, 4, 16)
+    for e, c in zip(ex.tolist(), hc.tolist()):
+        s = sum(e)
+        m40 = fact[40] // (fact[e[0]] * fact[e[1]] * fact[e[2]] * fact[e[3]] * fact[40 - s])
+        m20 = 0
+        if s <= 20:
+            m20 = fact[20] // (fact[e[0]] * fact[e[1]] * fact[e[2]] * fact[e[3]] * fact[20 - s])
+        assert c == (m40 + m20) % P
+    # evaluation at 16 random points mod p
+    import random
+    rr = random.Random(2)
+    for _ in range(16):
+        a = [rr.randrange(P) for _ in range(4)]
+        pw = [[pow(a[v], k, P) for k in range(41)] for v in range(4)]
+        s = 0
+        for e, c in zip(ex.tolist(), hc.tolist()):
+            s = (s + c * pw[0][e[0]] % P * pw[1][e[1]] % P * pw[2][e[2]] % P * pw[3][e[3]]) % P
+        fa = pow((1 + sum(a)) % P, 20, P)
+        assert s == fa * (fa + 1) % P
+
+
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_config3_full(ring):
+    f, g = W.config3(ring)
+    check(f, g, f"cfg3 {ring}")
+
+
+def test_config3_modp_sparse_path_forced_raw():
+    pm = _pm()
+    pm.set_tuning(-1, True, True)
+    f, g = W.config3("modp")
+    check(f, g, "cfg3 raw")
