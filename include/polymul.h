@@ -181,6 +181,25 @@ int pm_set_tuning(int32_t tile_cfg, int32_t force_raw, int32_t allow_dense);
  */
 int pm_last_call_status(void *stream);
 
+/*
+ * Size facts of the last pm_mul / pm_mul_batch call on this thread, after
+ * synchronising `stream`: pairs staged for the radix sort (after the LDS
+ * combine), radix passes, bytes per sort key, and degree-box cells (dense
+ * path).  Any pointer may be NULL.
+ */
+int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int32_t *key_bytes, int64_t *box_cells);
+
+/*
+ * Kernel timing.  pm_profile_enable(1) clears and starts recording a HIP
+ * event pair around every kernel the library launches (on the call's own
+ * stream); pm_profile_enable(0) stops.  pm_profile_read(i, ...) synchronises
+ * the recorded events and returns, for the i-th distinct kernel name, the
+ * name, summed duration in milliseconds and launch count; it returns the
+ * number of distinct names (so i may range over [0, return value)).
+ */
+int pm_profile_enable(int32_t enable);
+int pm_profile_read(int32_t i, char *name, int32_t name_cap, double *total_ms, int64_t *launches);
+
 /* Static message for an error code. */
 const char *pm_strerror(int code);
 /* Message of the last PM_EDEVICE error raised on the calling thread. */

@@ -16,6 +16,12 @@ namespace pm {
 
 static thread_local std::string g_last_error;
 static thread_local void *g_last_counters = nullptr;
+struct LastCall {
+    void *dyn = nullptr;
+    int nseg = 0, passes = 0, ksize = 0;
+    int64_t box = 0;
+};
+static thread_local LastCall g_last;
 
 void set_error(const char *what, hipError_t e) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -189,6 +195,11 @@ int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStr
     }
     hs.used = true;
     g_last_counters = (char *)ws + P.o_counters;
+    g_last.dyn = (char *)ws + P.o_dyn;
+    g_last.nseg = P.nseg;
+    g_last.passes = P.passes;
+    g_last.ksize = P.ksize;
+    g_last.box = P.nbox;
     Ctx C = make_ctx(P, ws);
     e = launch_pipeline(P, C, st, device_cus());
     if (e != hipSuccess) {
@@ -305,6 +316,35 @@ int pm_set_tuning(int32_t tile_cfg, int32_t force_raw, int32_t allow_dense) {
     g_tune.force_raw = force_raw ? 1 : 0;
     g_tune.allow_dense = allow_dense ? 1 : 0;
     return PM_OK;
+}
+
+int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int32_t *key_bytes, int64_t *box_cells) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("hipStreamSynchronize", e);
+        return PM_EDEVICE;
+    }
+    int64_t staged = 0;
+    if (g_last.dyn && g_last.nseg > 0) {
+        std::vector<DevSegDyn> d(g_last.nseg);
+        e = hipMemcpy(d.data(), g_last.dyn, sizeof(DevSegDyn) * g_last.nseg, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            set_error("hipMemcpy", e);
+            return PM_EDEVICE;
+        }
+        for (auto &x : d) staged += x.n;
+    }
+    if (staged_pairs) *staged_pairs = staged;
+    if (passes) *passes = g_last.passes;
+    if (key_bytes) *key_bytes = g_last.ksize;
+    if (box_cells) *box_cells = g_last.box;
+    return PM_OK;
+}
+
+int pm_profile_enable(int32_t enable) { return profile_enable(enable); }
+
+int pm_profile_read(int32_t i, char *name, int32_t name_cap, double *total_ms, int64_t *launches) {
+    return profile_read(i, name, name_cap, total_ms, launches);
 }
 
 const char *pm_strerror(int code) {

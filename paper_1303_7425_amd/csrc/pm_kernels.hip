@@ -643,20 +643,124 @@ __global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
 // ===========================================================================
 // Host-side launch sequence
 // ===========================================================================
+#include <string.h>
+
 #include "pm_launch.hpp"
 
+#include <mutex>
+#include <string>
+#include <vector>
+
 namespace pm {
+
+// Event-pair recorder around kernel launches (see pm_profile_enable).
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::string> names;
+    struct Rec {
+        int name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    std::vector<double> ms;
+    std::vector<int64_t> count;
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    int begin(const char *name, hipStream_t st) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!on) return -1;
+        int id = -1;
+        for (size_t i = 0; i < names.size(); i++)
+            if (names[i] == name) id = (int)i;
+        if (id < 0) {
+            names.push_back(name);
+            ms.push_back(0);
+            count.push_back(0);
+            id = (int)names.size() - 1;
+        }
+        Rec r{id, get(), get()};
+        (void)hipEventRecord(r.a, st);
+        recs.push_back(r);
+        return (int)recs.size() - 1;
+    }
+    void end(int rec, hipStream_t st) {
+        if (rec < 0) return;
+        std::lock_guard<std::mutex> lk(mu);
+        if (rec < (int)recs.size()) (void)hipEventRecord(recs[rec].b, st);
+    }
+    void collect() {
+        for (auto &r : recs) {
+            (void)hipEventSynchronize(r.b);
+            float t = 0;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                ms[r.name] += t;
+                count[r.name] += 1;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+};
+static Profiler g_prof;
+
+struct ProfScope {
+    int rec;
+    hipStream_t st;
+    ProfScope(const char *name, hipStream_t s) : rec(g_prof.begin(name, s)), st(s) {}
+    ~ProfScope() { g_prof.end(rec, st); }
+};
+
+int profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (on) {
+        g_prof.collect();
+        g_prof.names.clear();
+        g_prof.ms.clear();
+        g_prof.count.clear();
+    }
+    g_prof.on = on != 0;
+    return 0;
+}
+
+int profile_read(int i, char *name, int cap, double *total_ms, int64_t *launches) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.collect();
+    const int n = (int)g_prof.names.size();
+    if (i >= 0 && i < n) {
+        if (name && cap > 0) {
+            strncpy(name, g_prof.names[i].c_str(), cap - 1);
+            name[cap - 1] = 0;
+        }
+        if (total_ms) *total_ms = g_prof.ms[i];
+        if (launches) *launches = g_prof.count[i];
+    }
+    return n;
+}
 
 static inline int grid_for(int64_t work, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(work, cap)); }
 
 hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int ring, u64 *out, u32 *flags,
                         hipStream_t st) {
+    ProfScope ps("stats", st);
     hipLaunchKernelGGL(k_stats, dim3(2 * nseg), dim3(NTHREADS), 0, st, segs, nvars, bits, ring, out, flags);
     return hipGetLastError();
 }
 
 template <typename K, int RING>
 static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid) {
+    ProfScope ps("tile_combine", st);
     switch (P.tile_cfg) {
         case 0: hipLaunchKernelGGL((k_tile<K, RING, 32, 64, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
         case 1: hipLaunchKernelGGL((k_tile<K, RING, 64, 64, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
@@ -667,6 +771,7 @@ static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid) {
 template <typename K, int RING>
 static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
     if (P.nck > 0) {
+        ProfScope ps("compress", st);
         hipLaunchKernelGGL((k_compress<K>), dim3(grid_for((P.nck + NTHREADS - 1) / NTHREADS, cus * 16)), dim3(NTHREADS),
                            0, st, C, (const i64 *)((const char *)C.segs - P.o_segs + P.o_cpre), (i64)P.nck);
     }
@@ -674,19 +779,25 @@ static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
         if constexpr (RING != RING_F64) launch_tile<K, RING>(P, C, st, grid_for(P.ntiles, cus * 8));
     }
     if (P.nraw > 0) {
+        ProfScope ps("expand_raw", st);
         hipLaunchKernelGGL((k_expand_raw<K, RING>), dim3(grid_for(P.nraw, cus * 8)), dim3(NTHREADS), 0, st, C);
     }
     if (P.nsparse > 0) {
-        hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
-        if (P.passes > 0) hipLaunchKernelGGL(k_seg_bases, dim3(P.nseg), dim3(RADIX), 0, st, C);
+        {
+            ProfScope ps("seg_prepare", st);
+            hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
+            if (P.passes > 0) hipLaunchKernelGGL(k_seg_bases, dim3(P.nseg), dim3(RADIX), 0, st, C);
+        }
         K *ka = (K *)C.stA_k, *kb = (K *)C.stB_k;
         u64 *va = C.stA_v, *vb = C.stB_v;
         const int g = grid_for(P.nparts_bound, cus * 3);
         for (int pass = 0; pass < P.passes; pass++) {
+            ProfScope ps("onesweep", st);
             hipLaunchKernelGGL((k_onesweep<K>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
             std::swap(ka, kb);
             std::swap(va, vb);
         }
+        ProfScope ps("reduce", st);
         hipLaunchKernelGGL((k_reduce<K, RING>), dim3(grid_for(P.nparts_bound, cus * 3)), dim3(NTHREADS), 0, st, C,
                            ka, va);
     } else if (P.nseg > 0) {
@@ -694,6 +805,7 @@ static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
         hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
     }
     if (P.ndparts > 0) {
+        ProfScope ps("compact", st);
         if constexpr (RING != RING_F64)
             hipLaunchKernelGGL((k_compact<RING>), dim3(grid_for(P.ndparts, cus * 8)), dim3(NTHREADS), 0, st, C);
     }
@@ -703,8 +815,11 @@ hipError_t launch_pipeline(const Plan &P, const Ctx &C, hipStream_t st, int cus)
     // per-call zeroed state
     const size_t zbytes = P.r_zero.bytes;
     u64 *zp = (u64 *)((char *)C.segs - P.o_segs + P.r_zero.off);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(zbytes / 8 + 255) / 256, cus * 8)), dim3(256), 0, st, zp,
-                       (i64)(zbytes / 8), 0ull);
+    {
+        ProfScope ps("fill", st);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(zbytes / 8 + 255) / 256, cus * 8)), dim3(256), 0, st, zp,
+                           (i64)(zbytes / 8), 0ull);
+    }
     if (P.ksize == 4) {
         if (P.ring == RING_MODP) launch_typed<u32, RING_MODP>(P, C, st, cus);
         else if (P.ring == RING_I64) launch_typed<u32, RING_I64>(P, C, st, cus);

@@ -12,6 +12,8 @@ hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int r
 // Everything after validation: zero the per-call state, compress keys, tile /
 // expand, radix passes, reduction and dense compaction.  Enqueued on `st`.
 hipError_t launch_pipeline(const Plan &P, const Ctx &C, hipStream_t st, int cus);
+int profile_enable(int on);
+int profile_read(int i, char *name, int cap, double *total_ms, int64_t *launches);
 // Device pointers of every workspace region of plan P placed at `ws`.
 Ctx make_ctx(const Plan &P, void *ws);
 

@@ -70,6 +70,11 @@ def lib():
                                          ctypes.POINTER(ctypes.c_uint64), i64p, i64p]
         L.pm_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.pm_last_call_status.argtypes = [vp]
+        L.pm_last_call_info.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        i64p]
+        L.pm_profile_enable.argtypes = [ctypes.c_int32]
+        L.pm_profile_read.argtypes = [ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_double), i64p]
         L.pm_strerror.restype = ctypes.c_char_p
         L.pm_strerror.argtypes = [ctypes.c_int]
         L.pm_last_error.restype = ctypes.c_char_p
@@ -199,6 +204,34 @@ def mul(layout, f: DevPoly, g: DevPoly, out=None, workspace: Workspace | None = 
     return DevPoly(hk, hc, n, ring)
 
 
+class MulCall:
+    """A prepared pm_mul call: bound, output arrays and workspace allocated once;
+    `run()` enqueues the product (validation included) on the stream."""
+
+    def __init__(self, layout, f: DevPoly, g: DevPoly, workspace: Workspace | None = None, stream=None):
+        self.L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+        self.ring = {v: k for k, v in RING_CODE.items()}[self.L.ring]
+        self.f, self.g, self.stream = f, g, stream
+        self.cf, self.cg = _cpoly(f), _cpoly(g)
+        self.cap, self.ws_bytes = bound(self.L, f, g, stream)
+        self.out = alloc_out(self.cap, self.ring)
+        hk, hc, hn = self.out
+        self.h = pm_poly(self.cap, hn.data_ptr(), hk.data_ptr(), hc.data_ptr())
+        self.ws = (workspace or Workspace()).get(self.ws_bytes)
+        self.sp = _stream_ptr(stream)
+
+    def run(self):
+        _check(lib().pm_mul(ctypes.byref(self.L), ctypes.byref(self.cf), ctypes.byref(self.cg),
+                            ctypes.byref(self.h), ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), self.sp),
+               "pm_mul")
+
+    def n(self) -> int:
+        return int(self.out[2].item())
+
+    def result(self) -> DevPoly:
+        return DevPoly(self.out[0], self.out[1], self.n(), self.ring)
+
+
 class BatchCall:
     """A prepared pm_mul_batch call: bound, outputs and workspace allocated once,
     then `run()` enqueues the batch (re-validating the operands each time)."""
@@ -262,6 +295,31 @@ def mul_batch(layout, fs, gs, workspace=None, stream=None):
 def last_call_status(stream=None):
     """PM_OK unless the last call on this thread tripped a device-side check."""
     return int(lib().pm_last_call_status(_stream_ptr(stream)))
+
+
+def last_call_info(stream=None):
+    """(staged pairs, radix passes, key bytes, degree-box cells) of the last call."""
+    sp, bc = ctypes.c_int64(0), ctypes.c_int64(0)
+    ps, kb = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().pm_last_call_info(_stream_ptr(stream), ctypes.byref(sp), ctypes.byref(ps), ctypes.byref(kb),
+                                   ctypes.byref(bc)), "pm_last_call_info")
+    return int(sp.value), int(ps.value), int(kb.value), int(bc.value)
+
+
+def profile_enable(on: bool):
+    lib().pm_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """{kernel name: (total ms, launches)} of the recorded launches."""
+    out = {}
+    n = lib().pm_profile_read(-1, None, 0, None, None)
+    for i in range(n):
+        buf = ctypes.create_string_buffer(64)
+        ms, cnt = ctypes.c_double(0), ctypes.c_int64(0)
+        lib().pm_profile_read(i, buf, 64, ctypes.byref(ms), ctypes.byref(cnt))
+        out[buf.value.decode()] = (float(ms.value), int(cnt.value))
+    return out
 
 
 def set_tuning(tile_cfg: int = -1, force_raw: bool = False, allow_dense: bool = True):
