@@ -83,12 +83,13 @@ def main():
     torch.cuda.synchronize()
     prof = pm.profile_read()
     pm.profile_enable(False)
-    staged, passes, kbytes, _ = pm.last_call_info()
+    info = pm.last_call_info()
+    staged, passes, kbytes, vbytes = info["staged"], info["passes"], info["key_bytes"], info["payload_bytes"]
     assert pm.last_call_status() == 0
     per_step = {k: round(v[0] / args.steps, 5) for k, v in prof.items()}
     sweep_ms, sweep_n = prof.get("onesweep", (0.0, 0))
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
-    sweep_bytes = staged * (kbytes + 8) * 2  # read key+value, write key+value
+    sweep_bytes = staged * (kbytes + vbytes) * 2  # read key+payload, write key+payload
     achieved = sweep_bytes / (sweep_avg_ms * 1e-3) / 1e9 if sweep_avg_ms > 0 else 0.0
 
     cpu = None
@@ -126,7 +127,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "onesweep (one LSD radix pass)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": sweep_bytes, "avg_launch_ms": sweep_avg_ms,
-                     "staged_pairs": staged, "passes": passes, "key_bytes": kbytes},
+                     "sorted_items": staged, "passes": passes, "key_bytes": kbytes,
+                     "payload_bytes": vbytes},
         "kernel_ms_per_step": per_step,
         "cpu_baseline": cpu,
     }

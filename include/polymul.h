@@ -166,11 +166,15 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
 /*
  * Process-wide tuning of later calls (the autotuner's knobs):
  *   tile_cfg     -1 automatic, else 0: 32x64, 1: 64x64, 2: 128x128 term tiles
- *   force_raw    1: exact rings skip the LDS combine and stage every product
+ *                (LDS tile combine and dense path)
+ *   combine      -1 automatic; 0: the sparse path radix-sorts term-pair indices
+ *                and regenerates each product in the reduction; 1: exact rings
+ *                first combine f-block x g-block tiles in LDS and sort the
+ *                combined (monomial, coefficient) pairs
  *   allow_dense  0: never use the degree-box path
- * Results do not depend on these settings.
+ * Results do not depend on these settings (FP64 always sorts pair indices).
  */
-int pm_set_tuning(int32_t tile_cfg, int32_t force_raw, int32_t allow_dense);
+int pm_set_tuning(int32_t tile_cfg, int32_t combine, int32_t allow_dense);
 
 /*
  * Synchronises `stream`, then reports whether the last pm_mul / pm_mul_batch
@@ -183,11 +187,12 @@ int pm_last_call_status(void *stream);
 
 /*
  * Size facts of the last pm_mul / pm_mul_batch call on this thread, after
- * synchronising `stream`: pairs staged for the radix sort (after the LDS
- * combine), radix passes, bytes per sort key, and degree-box cells (dense
- * path).  Any pointer may be NULL.
+ * synchronising `stream`: items radix-sorted (term pairs, or combined pairs
+ * after the LDS tile combine), radix passes, bytes per sort key and per sort
+ * payload, and degree-box cells (dense path).  Any pointer may be NULL.
  */
-int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int32_t *key_bytes, int64_t *box_cells);
+int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int32_t *key_bytes,
+                      int32_t *payload_bytes, int64_t *box_cells);
 
 /*
  * Kernel timing.  pm_profile_enable(1) clears and starts recording a HIP

@@ -18,7 +18,7 @@ static thread_local std::string g_last_error;
 static thread_local void *g_last_counters = nullptr;
 struct LastCall {
     void *dyn = nullptr;
-    int nseg = 0, passes = 0, ksize = 0;
+    int nseg = 0, passes = 0, ksize = 0, vsize = 0;
     int64_t box = 0;
 };
 static thread_local LastCall g_last;
@@ -182,8 +182,6 @@ int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStr
     if (!P.vars.empty()) memcpy(pin + (P.o_vars - d0), P.vars.data(), sizeof(VarParam) * P.vars.size());
     memcpy(pin + (P.o_tile_pre - d0), P.tile_pre.data(), 8 * P.tile_pre.size());
     if (!P.tile_seg.empty()) memcpy(pin + (P.o_tile_seg - d0), P.tile_seg.data(), 4 * P.tile_seg.size());
-    memcpy(pin + (P.o_raw_pre - d0), P.raw_pre.data(), 8 * P.raw_pre.size());
-    if (!P.raw_seg.empty()) memcpy(pin + (P.o_raw_seg - d0), P.raw_seg.data(), 4 * P.raw_seg.size());
     memcpy(pin + (P.o_dpart_pre - d0), P.dpart_pre.data(), 8 * P.dpart_pre.size());
     if (!P.dseg.empty()) memcpy(pin + (P.o_dseg - d0), P.dseg.data(), 4 * P.dseg.size());
     memcpy(pin + (P.o_cpre - d0), P.cpre.data(), 8 * P.cpre.size());
@@ -199,6 +197,7 @@ int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStr
     g_last.nseg = P.nseg;
     g_last.passes = P.passes;
     g_last.ksize = P.ksize;
+    g_last.vsize = P.vsize;
     g_last.box = P.nbox;
     Ctx C = make_ctx(P, ws);
     e = launch_pipeline(P, C, st, device_cus());
@@ -309,16 +308,17 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
     return PM_OK;
 }
 
-int pm_set_tuning(int32_t tile_cfg, int32_t force_raw, int32_t allow_dense) {
+int pm_set_tuning(int32_t tile_cfg, int32_t combine, int32_t allow_dense) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (tile_cfg < -1 || tile_cfg >= N_TILE_CFGS) return PM_EINVAL;
+    if (tile_cfg < -1 || tile_cfg >= N_TILE_CFGS || combine < -1 || combine > 1) return PM_EINVAL;
     g_tune.tile_cfg = tile_cfg;
-    g_tune.force_raw = force_raw ? 1 : 0;
+    g_tune.combine = combine;
     g_tune.allow_dense = allow_dense ? 1 : 0;
     return PM_OK;
 }
 
-int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int32_t *key_bytes, int64_t *box_cells) {
+int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int32_t *key_bytes,
+                      int32_t *payload_bytes, int64_t *box_cells) {
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) {
         set_error("hipStreamSynchronize", e);
@@ -337,6 +337,7 @@ int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int3
     if (staged_pairs) *staged_pairs = staged;
     if (passes) *passes = g_last.passes;
     if (key_bytes) *key_bytes = g_last.ksize;
+    if (payload_bytes) *payload_bytes = g_last.vsize;
     if (box_cells) *box_cells = g_last.box;
     return PM_OK;
 }

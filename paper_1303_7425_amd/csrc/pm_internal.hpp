@@ -20,7 +20,7 @@ enum Ring : int { RING_MODP = 0, RING_F64 = 1, RING_I64 = 2 };
 enum SegMode : int {
     SEG_EMPTY = 0,    // an operand is empty: n_out = 0
     SEG_COMBINE = 1,  // tiles combined in LDS, then global radix sort + segmented reduction
-    SEG_RAW = 2,      // every term product staged in row-major order, then sort + reduction
+    SEG_RAW = 2,      // pair indices sorted by key (products regenerated), then reduction
     SEG_DENSE = 3,    // accumulated directly into the degree box, then compaction
 };
 
@@ -32,6 +32,33 @@ constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
 constexpr int MAX_VARS = 64;
 
+// Unsigned 32-bit division by an invariant divisor d >= 1 (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994):
+// q = (t + ((n - t) >> s1)) >> s2 with t = mulhi(m, n).
+struct Div32 {
+    u32 m, s1, s2, d;
+};
+
+inline Div32 make_div32(u32 d) {
+    int l = 0;
+    while (l < 32 && (1ull << l) < d) l++;
+    Div32 r;
+    r.m = (u32)(((((unsigned __int128)1) << 32) * ((((unsigned __int128)1) << l) - d)) / d + 1);
+    r.s1 = l < 1 ? l : 1;
+    r.s2 = l > 1 ? l - 1 : 0;
+    r.d = d;
+    return r;
+}
+
+__host__ __device__ inline u32 div32(u32 n, const Div32 &dv) {
+#ifdef __HIP_DEVICE_COMPILE__
+    u32 t = __umulhi(dv.m, n);
+#else
+    u32 t = (u32)(((u64)dv.m * n) >> 32);
+#endif
+    return (t + ((n - t) >> dv.s1)) >> dv.s2;
+}
+
 // Per-product descriptor, uploaded once per call.
 struct DevSeg {
     const u64 *fk, *fc, *gk, *gc;  // operand keys / coefficient bits
@@ -41,8 +68,7 @@ struct DevSeg {
     i64 stage_bound;               // staging slots (sparse) or box cells (dense)
     i64 tile_first;                // first tile of this product in the tile queue
     i64 tiles_n;                   // tiles along g
-    i64 raw_first;                 // first row-chunk block (SEG_RAW)
-    i64 raw_chunks;                // row chunks per row (SEG_RAW)
+    Div32 nb_div;                  // division by nb: pair index -> (row, column) (SEG_RAW)
     i64 dpart_first;               // first compaction partition (SEG_DENSE)
     i64 var_off;                   // offset of this product's VarParam entries
     u64 lo_key;                    // packed key of the smallest output exponent vector
@@ -73,6 +99,7 @@ struct VarParam {
     u64 minf, ming;
     u64 range;
     u64 stride;
+    Div32 rdiv;  // division by range (when range < 2^32)
 };
 
 // Launch-wide context passed by value to every kernel.
@@ -82,30 +109,30 @@ struct Ctx {
     VarParam *vars;
     const i64 *tile_pre;    // [ntseg+1] exclusive tile prefix over tiled segments
     const i32 *tile_seg;    // [ntseg] segment index of each tiled segment
-    const i64 *raw_pre;     // [nrseg+1] row-chunk block prefix over SEG_RAW segments
-    const i32 *raw_seg;
     const i64 *dpart_pre;   // [ndseg+1] compaction partition prefix over SEG_DENSE segments
     const i32 *dseg;
     i64 *ppre;              // [nseg+1] sort partition prefix (device computed)
     void *ck;               // compressed operand keys
-    void *stA_k; u64 *stA_v;
-    void *stB_k; u64 *stB_v;
+    void *stA_k, *stA_v;
+    void *stB_k, *stB_v;
     u64 *box;
-    unsigned long long *hist;   // [passes][nseg][RADIX]
-    u64 *bases;                 // [passes][nseg][RADIX]
+    unsigned long long *hist;   // [passes][nseg][RADIX] digit counts per product
     u64 *look;                  // sort lookback [nparts_bound][RADIX]
     u64 *look_red;              // reduce lookback [nparts_bound]
     u64 *look_cmp;              // dense compaction lookback [ndparts]
+    u64 *look_tile;             // staging offsets of combined tiles [ntiles]
     u32 *counters;              // work-queue tickets and error flags
-    i32 nseg, ntseg, nrseg, ndseg;
+    i32 nseg, ntseg, ndseg;
     i32 nvars, bits, passes, ring;
-    i64 ntiles, nraw, ndparts;
+    i64 ntiles, ndparts;
+    i32 raw;                    // sparse products carry pair indices (SEG_RAW) instead of values
+    i32 tb_tile, tb_sort, tb_cmp;  // consecutive work items handed out per work-queue ticket
 };
 
 // counters[] slots
 enum Counter : int {
     CNT_TILE = 0,
-    CNT_RAW = 1,
+    CNT_HIST = 1,
     CNT_SORT = 2,                   // + pass (MAX_PASSES slots)
     CNT_REDUCE = CNT_SORT + MAX_PASSES,
     CNT_COMPACT,
@@ -279,6 +306,97 @@ __device__ inline u64 lookback(u64 *look, i64 stride, i64 first, i64 p, u32 tag,
     return prefix;
 }
 
+__device__ inline u64 wave_sum_u64(u64 v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Per-thread decoupled look-back over a strided counter array (one counter
+// per digit), reading up to four predecessors per round trip.
+__device__ inline u64 lookback_batched(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
+    if (p == first) {
+        lb_store(look + p * stride, lb_pack(tag, LB_INC, value));
+        return 0;
+    }
+    lb_store(look + p * stride, lb_pack(tag, LB_AGG, value));
+    u64 prefix = 0;
+    i64 j = p - 1;
+    u32 spins = 0;
+    while (true) {
+        u64 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[k] = (j - k >= first) ? lb_load(look + (j - k) * stride) : 0;
+        bool done = false;
+        int used = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (done || used < k) break;
+            if (j - k < first) {
+                done = true;
+                break;
+            }
+            if ((u32)(v[k] >> 56) != tag) break;
+            prefix += v[k] & ((1ull << 54) - 1);
+            used++;
+            if (((v[k] >> 54) & 3) == LB_INC) done = true;
+        }
+        if (done) break;
+        j -= used;
+        if (j < first) break;
+        if (used == 0 && ++spins > LB_SPIN_LIMIT) {
+            atomicOr(err, 1u);
+            break;
+        }
+    }
+    lb_store(look + p * stride, lb_pack(tag, LB_INC, prefix + value));
+    return prefix;
+}
+
+// Wave-cooperative decoupled look-back for one counter per partition.  All
+// 64 lanes of one wave call it with the same (first, p); lane l inspects
+// predecessor p-1-l, so one round trip covers 64 predecessors.  Returns the
+// exclusive prefix of `value` over partitions [first, p) in every lane.
+__device__ inline u64 lookback_wave(u64 *look, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
+    const u32 lane = lane_id();
+    if (p == first) {
+        if (lane == 0) lb_store(look + p, lb_pack(tag, LB_INC, value));
+        return 0;
+    }
+    if (lane == 0) lb_store(look + p, lb_pack(tag, LB_AGG, value));
+    u64 prefix = 0;
+    i64 top = p - 1;
+    while (true) {
+        const i64 j = top - (i64)lane;
+        u64 val = 0;
+        bool inc = true;
+        if (j >= first) {
+            u64 v = lb_load(look + j);
+            u32 spins = 0;
+            while ((u32)(v >> 56) != tag && spins < LB_SPIN_LIMIT) {
+                spins++;
+                v = lb_load(look + j);
+            }
+            if ((u32)(v >> 56) != tag) {
+                atomicOr(err, 1u);
+            } else {
+                inc = ((v >> 54) & 3) == LB_INC;
+                val = v & ((1ull << 54) - 1);
+            }
+        }
+        const u64 im = __ballot(inc);
+        if (im) {
+            const u32 k = (u32)__ffsll((unsigned long long)im) - 1;  // nearest predecessor with a prefix
+            prefix += wave_sum_u64(lane <= k ? val : 0);
+            break;
+        }
+        prefix += wave_sum_u64(val);
+        top -= 64;
+    }
+    if (lane == 0) lb_store(look + p, lb_pack(tag, LB_INC, prefix + value));
+    return prefix;
+}
+
 // Largest index s in [0, n) with pre[s] <= x (pre ascending, pre[0] = 0).
 __device__ inline i32 seg_search(const i64 *pre, i32 n, i64 x) {
     i32 lo = 0, hi = n - 1;
@@ -294,17 +412,25 @@ __device__ inline i32 seg_search(const i64 *pre, i32 n, i64 x) {
 template <typename K>
 __device__ inline u64 decompress(K ck, const VarParam *vp, int nvars, u64 lo_key) {
     u64 key = lo_key;
-    for (int v = nvars - 1; v >= 0; v--) {
-        K r = (K)vp[v].range;
-        K e;
-        if (r == 0) {  // range 2^64: a single full-width variable
-            e = ck;
-            ck = 0;
-        } else {
-            e = ck % r;
-            ck /= r;
+    if constexpr (sizeof(K) == 4) {
+        for (int v = nvars - 1; v >= 0; v--) {
+            const u32 q = div32((u32)ck, vp[v].rdiv);
+            key += (u64)((u32)ck - q * vp[v].rdiv.d) << vp[v].shift;
+            ck = q;
         }
-        key += (u64)e << vp[v].shift;
+    } else {
+        for (int v = nvars - 1; v >= 0; v--) {
+            K r = (K)vp[v].range;
+            K e;
+            if (r == 0) {  // range 2^64: a single full-width variable
+                e = ck;
+                ck = 0;
+            } else {
+                e = ck % r;
+                ck /= r;
+            }
+            key += (u64)e << vp[v].shift;
+        }
     }
     return key;
 }

@@ -6,9 +6,10 @@
 //   k_tile       f-block x g-block tile of term products expanded into LDS and
 //                combined there with an LDS hash (exact rings); unique pairs go
 //                to a staging buffer (sparse) or into the degree-box array (dense)
-//   k_expand_raw every term product staged in row-major (i, j) order (FP64)
-//   k_seg_prepare / k_seg_bases   per-product sizes, partitions, digit offsets
-//   k_onesweep   one stable LSD radix pass (8-bit digit) with decoupled look-back
+//   k_hist_raw   digit histogram of products sorted by pair index (SEG_RAW)
+//   k_seg_prepare per-product sizes and sort partitions
+//   k_onesweep   one stable LSD radix pass (8-bit digit) with decoupled look-back;
+//                pass 0 of SEG_RAW generates its keys from the operands
 //   k_reduce     segmented like-term reduction + zero drop + key decompression
 //   k_compact    dense path: degree-box cells -> sorted non-zero terms
 //
@@ -113,23 +114,18 @@ __global__ __launch_bounds__(NTHREADS) void k_compress(Ctx C, const i64 *cpre, i
 }
 
 // ---------------------------------------------------------------------------
-// Per-pass digit histogram kept in LDS across the work items of one segment
-// and flushed to the global [pass][segment][digit] table.
+// Digit histograms.  hist[pass][segment][digit] holds the count of staged
+// keys with that digit; a workgroup accumulates in LDS while it stays on one
+// product and flushes with one global atomic per non-zero bin.
 // ---------------------------------------------------------------------------
-__device__ inline void hist_flush(Ctx &C, u32 *s_hist, int q) {
-    for (int e = threadIdx.x; e < C.passes * RADIX; e += NTHREADS) {
-        u32 v = s_hist[e];
+__device__ inline void hist_flush(Ctx &C, u32 *s_h, int pass, int q) {
+    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) {
+        const u32 v = s_h[d];
         if (v) {
-            const int p = e / RADIX, d = e % RADIX;
-            atomicAdd(C.hist + ((i64)p * C.nseg + q) * RADIX + d, (unsigned long long)v);
-            s_hist[e] = 0;
+            atomicAdd(C.hist + ((i64)pass * C.nseg + q) * RADIX + d, (unsigned long long)v);
+            s_h[d] = 0;
         }
     }
-}
-
-template <typename K>
-__device__ inline void hist_add(u32 *s_hist, int passes, K ck) {
-    for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p * RADIX + (u32)((ck >> (p * RADIX_BITS)) & (RADIX - 1))], 1u);
 }
 
 constexpr int MAX_PROBE = 32;
@@ -158,9 +154,9 @@ __device__ inline u32 hash_slot(K ck, int hb) {
 // a TM x TN block of the pp-matrix (Fig. 1).  Each term product is inserted
 // into an LDS open-addressing table keyed by its mixed-radix monomial index
 // and accumulated there exactly (mod p or modulo 2^64).  The table's non-zero
-// entries then go either to the product's staging region (sparse; the region
-// offset is reserved with one atomic per tile, order irrelevant for exact
-// rings) or into the degree-box array (dense).
+// entries then go either to the product's staging array (sparse; the offset
+// comes from a look-back over the product's earlier tiles, so the staging is
+// dense) or into the degree-box array (dense).
 // ---------------------------------------------------------------------------
 template <typename K, int RING, int TM, int TN, int HB>
 __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
@@ -169,20 +165,24 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
     const K EMPTY = (K)~(K)0;
     __shared__ K s_fk[TM], s_gk[TN];
     __shared__ u64 s_fc[TM], s_gc[TN];
-    __shared__ K s_hk[HS];
-    __shared__ u64 s_hv[HS];
-    __shared__ u32 s_hist[MAX_PASSES * RADIX];
+    __shared__ K s_hk[HS + HS / 16];   // padded: slot h lives at h + h/16
+    __shared__ u64 s_hv[HS + HS / 16];
+    __shared__ u32 s_h0[RADIX];
     __shared__ u32 s_scan[NTHREADS / 64];
     __shared__ i64 s_tile;
     __shared__ u64 s_base;
+    auto pad = [](int h) { return h + (h >> 4); };
 
-    for (int e = threadIdx.x; e < C.passes * RADIX; e += NTHREADS) s_hist[e] = 0;
+    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) s_h0[d] = 0;
     int cur_q = -1;
+    const i64 tb = C.tb_tile;
     while (true) {
-        if (threadIdx.x == 0) s_tile = (i64)atomicAdd(&C.counters[CNT_TILE], 1u);
+        if (threadIdx.x == 0) s_tile = (i64)atomicAdd(&C.counters[CNT_TILE], 1u) * tb;
         __syncthreads();
-        const i64 t = s_tile;
-        if (t >= C.ntiles) break;
+        const i64 t0 = s_tile;
+        if (t0 >= C.ntiles) break;
+        __syncthreads();
+        for (i64 t = t0; t < min(t0 + tb, C.ntiles); t++) {
         const i32 ts = seg_search(C.tile_pre, C.ntseg, t);
         const int q = C.tile_seg[ts];
         const DevSeg &s = C.segs[q];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
         const int tm = (int)min((i64)TM, s.na - i0), tn = (int)min((i64)TN, s.nb - j0);
         const bool dense = s.mode == SEG_DENSE;
         if (!dense && q != cur_q) {
-            if (cur_q >= 0) hist_flush(C, s_hist, cur_q);
+            if (cur_q >= 0 && C.passes > 0) hist_flush(C, s_h0, 0, cur_q);
             cur_q = q;
         }
         const K *ck = (const K *)C.ck;
@@ -206,11 +206,12 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
                 s_gc[e] = s.gc[j0 + e];
             }
         for (int e = threadIdx.x; e < HS; e += NTHREADS) {
-            s_hk[e] = EMPTY;
-            s_hv[e] = 0;
+            s_hk[pad(e)] = EMPTY;
+            s_hv[pad(e)] = 0;
         }
         __syncthreads();
         // expand + combine
+        const int max_probe = dense ? MAX_PROBE : HS;
         for (int e = threadIdx.x; e < TM * TN; e += NTHREADS) {
             const int i = e / TN, j = e % TN;
             if (i >= tm || j >= tn) continue;
@@ -219,8 +220,8 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
             const K key = s_fk[i] + s_gk[j];
             u32 h = hash_slot<K>(key, HB);
             bool found = false;
-            for (int probe = 0; probe < MAX_PROBE; probe++) {
-                K old = lds_cas<K>(&s_hk[h], EMPTY, key);
+            for (int probe = 0; probe < max_probe; probe++) {
+                K old = lds_cas<K>(&s_hk[pad(h)], EMPTY, key);
                 if (old == EMPTY || old == key) {
                     found = true;
                     break;
@@ -228,23 +229,20 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
                 h = (h + 1) & (HS - 1);
             }
             if (found) {
-                ring_atomic_acc<RING>(&s_hv[h], c);
+                ring_atomic_acc<RING>(&s_hv[pad(h)], c);
             } else if (dense) {
                 // table region saturated: accumulate this product in the box directly
                 ring_atomic_acc<RING>(C.box + s.stage_base + (u64)key, c);
             } else {
-                // stage the single product; the global reduction merges it later
-                const i64 slot = s.stage_base + (i64)atomicAdd(&C.dyn[q].fill, 1ull);
-                ((K *)C.stA_k)[slot] = key;
-                C.stA_v[slot] = c;
-                hist_add<K>(s_hist, C.passes, key);
+                // cannot happen: combine tiles hold at most half as many products as slots
+                atomicOr(&C.counters[CNT_ERR_SPIN], 4u);
             }
         }
         __syncthreads();
         // compaction of the table: thread owns slots [tid*SPT, tid*SPT+SPT)
         u32 cnt = 0;
         for (int r = 0; r < SPT; r++) {
-            const int h = threadIdx.x * SPT + r;
+            const int h = pad(threadIdx.x * SPT + r);
             if (s_hk[h] != EMPTY && !ring_is_zero<RING>(ring_cell_final<RING>(s_hv[h]))) cnt++;
         }
         u32 total;
@@ -252,91 +250,91 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
         if (dense) {
             u64 *box = C.box + s.stage_base;
             for (int r = 0; r < SPT; r++) {
-                const int h = threadIdx.x * SPT + r;
+                const int h = pad(threadIdx.x * SPT + r);
                 if (s_hk[h] == EMPTY) continue;
                 u64 v = ring_cell_final<RING>(s_hv[h]);
                 if (!ring_is_zero<RING>(v)) ring_atomic_acc<RING>(box + (u64)s_hk[h], v);
             }
         } else {
-            if (threadIdx.x == 0) s_base = total ? atomicAdd(&C.dyn[q].fill, (unsigned long long)total) : 0;
+            // dense staging offset: look-back over this product's earlier tiles
+            const i64 tfirst = C.tile_pre[ts];
+            if (threadIdx.x < 64) {
+                const u64 pre = lookback_wave(C.look_tile, tfirst, t, 202u, total, &C.counters[CNT_ERR_SPIN]);
+                if (threadIdx.x == 0) {
+                    s_base = pre;
+                    if (t == C.tile_pre[ts + 1] - 1) C.dyn[q].fill = pre + total;
+                }
+            }
             __syncthreads();
             const i64 base = s.stage_base + (i64)s_base + off;
             K *sk = (K *)C.stA_k;
+            u64 *sv = (u64 *)C.stA_v;
             u32 w = 0;
             for (int r = 0; r < SPT; r++) {
-                const int h = threadIdx.x * SPT + r;
+                const int h = pad(threadIdx.x * SPT + r);
                 if (s_hk[h] == EMPTY) continue;
                 u64 v = ring_cell_final<RING>(s_hv[h]);
                 if (ring_is_zero<RING>(v)) continue;
                 sk[base + w] = s_hk[h];
-                C.stA_v[base + w] = v;
-                hist_add<K>(s_hist, C.passes, s_hk[h]);
+                sv[base + w] = v;
+                if (C.passes > 0) atomicAdd(&s_h0[(u32)s_hk[h] & (RADIX - 1)], 1u);
                 w++;
             }
         }
         __syncthreads();
+        }
     }
-    if (cur_q >= 0) {
+    if (cur_q >= 0 && C.passes > 0) {
         __syncthreads();
-        hist_flush(C, s_hist, cur_q);
+        hist_flush(C, s_h0, 0, cur_q);
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_expand_raw: SEG_RAW products.  Work item = (segment, row i, chunk of
-// RAW_CHUNK columns).  Pair (i, j) goes to staging slot i*nb + j, so staging
-// order is the row-major order of the pp-matrix.
+// SEG_RAW products: pair (i, j) of the pp-matrix has index x = i*nb + j; the
+// sort carries (key, x) and the reduction regenerates a_i * b_j from x.
+// k_hist_raw: digit-0 histogram of every pair key, generated on the fly.
 // ---------------------------------------------------------------------------
-constexpr int RAW_CHUNK = 4096;
+template <typename K>
+__device__ inline K raw_key(const DevSeg &s, const K *ck, u32 x) {
+    const u32 i = div32(x, s.nb_div);
+    const u32 j = x - i * (u32)s.nb;
+    return ck[s.ck_f + i] + ck[s.ck_g + j];
+}
 
-template <typename K, int RING>
-__global__ __launch_bounds__(NTHREADS) void k_expand_raw(Ctx C) {
-    __shared__ u32 s_hist[MAX_PASSES * RADIX];
-    __shared__ i64 s_item;
-    for (int e = threadIdx.x; e < C.passes * RADIX; e += NTHREADS) s_hist[e] = 0;
+template <typename K>
+__global__ __launch_bounds__(NTHREADS) void k_hist_raw(Ctx C) {
+    __shared__ u32 s_h[RADIX];
+    __shared__ i64 s_p;
+    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) s_h[d] = 0;
     int cur_q = -1;
+    const i64 nparts = C.ppre[C.nseg];
     const K *ck = (const K *)C.ck;
-    K *sk = (K *)C.stA_k;
-    while (true) {
-        if (threadIdx.x == 0) s_item = (i64)atomicAdd(&C.counters[CNT_RAW], 1u);
-        __syncthreads();
-        const i64 t = s_item;
-        __syncthreads();
-        if (t >= C.nraw) break;
-        const i32 rs = seg_search(C.raw_pre, C.nrseg, t);
-        const int q = C.raw_seg[rs];
-        const DevSeg &s = C.segs[q];
+    (void)s_p;
+    for (i64 p = blockIdx.x; p < nparts; p += gridDim.x) {
+        const int q = seg_search(C.ppre, C.nseg, p);
         if (q != cur_q) {
-            if (cur_q >= 0) {
-                __syncthreads();
-                hist_flush(C, s_hist, cur_q);
-                __syncthreads();
-            }
+            __syncthreads();
+            if (cur_q >= 0) hist_flush(C, s_h, 0, cur_q);
+            __syncthreads();
             cur_q = q;
         }
-        const i64 local = t - C.raw_pre[rs];
-        const i64 i = local / s.raw_chunks;
-        const i64 j0 = (local % s.raw_chunks) * RAW_CHUNK;
-        const i64 jn = min((i64)RAW_CHUNK, s.nb - j0);
-        const K fkey = ck[s.ck_f + i];
-        const u64 fcv = s.fc[i];
-        const i64 base = s.stage_base + i * s.nb + j0;
-        for (i64 j = threadIdx.x; j < jn; j += NTHREADS) {
-            const K key = fkey + ck[s.ck_g + j0 + j];
-            sk[base + j] = key;
-            C.stA_v[base + j] = ring_mul<RING>(fcv, s.gc[j0 + j]);
-            hist_add<K>(s_hist, C.passes, key);
-        }
+        const DevSeg &s = C.segs[q];
+        const i64 c = p - C.ppre[q];
+        const i64 n_q = C.dyn[q].n;
+        const int n = (int)min((i64)PART, n_q - c * PART);
+        const u32 x0 = (u32)(c * PART);
+        for (int e = threadIdx.x; e < n; e += NTHREADS)
+            atomicAdd(&s_h[(u32)raw_key<K>(s, ck, x0 + e) & (RADIX - 1)], 1u);
     }
     if (cur_q >= 0) {
         __syncthreads();
-        hist_flush(C, s_hist, cur_q);
+        hist_flush(C, s_h, 0, cur_q);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Per-product sizes and sort partitions (one workgroup), then per-product
-// exclusive digit offsets for every pass (one workgroup per product).
+// Per-product sizes and sort partitions (one workgroup).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
     __shared__ i64 s_scan[NTHREADS / 64];
@@ -369,55 +367,70 @@ __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
     if (threadIdx.x == 0) C.ppre[C.nseg] = s_carry;
 }
 
-__global__ __launch_bounds__(RADIX) void k_seg_bases(Ctx C) {
-    __shared__ u64 s_scan[RADIX / 64];
-    const int q = blockIdx.x;
-    const DevSeg &s = C.segs[q];
-    if (s.mode != SEG_COMBINE && s.mode != SEG_RAW) return;
-    for (int p = 0; p < C.passes; p++) {
-        const i64 idx = ((i64)p * C.nseg + q) * RADIX + threadIdx.x;
-        u64 tot;
-        u64 off = block_excl_scan<u64>((u64)C.hist[idx], s_scan, tot);
-        C.bases[idx] = (u64)s.stage_base + off;
-    }
+// Digit offsets of product q for one pass: s_base[d] = stage_base + number of
+// the product's keys with a smaller digit.  Whole workgroup.
+__device__ inline void seg_digit_bases(Ctx &C, int pass, int q, u64 *s_base, u64 *s_scan64) {
+    const int d = threadIdx.x;  // RADIX == NTHREADS
+    const u64 h = C.hist[((i64)pass * C.nseg + q) * RADIX + d];
+    u64 tot;
+    const u64 off = block_excl_scan<u64>(h, s_scan64, tot);
+    s_base[d] = (u64)C.segs[q].stage_base + off;
 }
 
 // ---------------------------------------------------------------------------
 // k_onesweep: one stable LSD radix pass over digit `pass` of every product's
-// staged keys.  Partition = PART consecutive pairs of one product.  Ranks are
-// computed per wave with ballot "match" masks (peers with the same digit),
-// per-wave digit counters in LDS and a workgroup scan; the product-wide
-// position of each digit comes from the product's digit offsets plus a
-// decoupled look-back over the product's earlier partitions.  Keys and values
-// are permuted through LDS so that global writes are contiguous per digit.
+// staged keys, carrying a payload V (the coefficient for SEG_COMBINE, the
+// pair index for SEG_RAW).  Partition = PART consecutive items of one
+// product.  Ranks come from per-wave ballot "match" masks (peers with the same
+// digit) and per-wave digit counters in LDS; a digit's product-wide position
+// is its digit offset plus a decoupled look-back over the product's earlier
+// partitions.  GEN: pass 0 of SEG_RAW, where items are generated from the
+// pair index instead of read.  The histogram of the next digit is counted on
+// the way (input and output are the same multiset).
 // ---------------------------------------------------------------------------
-template <typename K>
+template <typename K, typename V, bool GEN>
 __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
-                                                        const u64 *__restrict__ vin, K *__restrict__ kout,
-                                                        u64 *__restrict__ vout) {
+                                                        const V *__restrict__ vin, K *__restrict__ kout,
+                                                        V *__restrict__ vout) {
     constexpr int NW = NTHREADS / 64;
     __shared__ union {
         K k[PART];
-        u64 v[PART];
+        V v[PART];
     } s_buf;
     __shared__ unsigned char s_dig[PART];
     __shared__ u32 s_wh[NW][RADIX];
     __shared__ u32 s_loff[RADIX];
     __shared__ i64 s_goff[RADIX];
+    __shared__ u64 s_base[RADIX];
+    __shared__ u32 s_nh[RADIX];
     __shared__ u32 s_scan[NW];
+    __shared__ u64 s_scan64[NW];
     __shared__ i64 s_p;
 
     const int shift = pass * RADIX_BITS;
+    const bool next_hist = pass + 1 < C.passes;
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
     const u32 tag = (u32)pass + 1;
     const i64 nparts = C.ppre[C.nseg];
+    const K *ckeys = (const K *)C.ck;
+    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) s_nh[d] = 0;
+    int cur_q = -1;
+    const i64 tb = C.tb_sort;
     while (true) {
-        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_SORT + pass], 1u);
+        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_SORT + pass], 1u) * tb;
+        __syncthreads();
+        const i64 p0 = s_p;
+        if (p0 >= nparts) break;
+        __syncthreads();
+        for (i64 p = p0; p < min(p0 + tb, nparts); p++) {
         for (int d = threadIdx.x; d < NW * RADIX; d += NTHREADS) (&s_wh[0][0])[d] = 0;
         __syncthreads();
-        const i64 p = s_p;
-        if (p >= nparts) break;
         const int q = seg_search(C.ppre, C.nseg, p);
+        if (q != cur_q) {
+            if (cur_q >= 0 && next_hist) hist_flush(C, s_nh, pass + 1, cur_q);
+            seg_digit_bases(C, pass, q, s_base, s_scan64);
+            cur_q = q;
+        }
         const DevSeg &s = C.segs[q];
         const i64 first = C.ppre[q];
         const i64 c = p - first;
@@ -425,14 +438,29 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
         const i64 start = s.stage_base + c * PART;
         const int n = (int)min((i64)PART, n_q - c * PART);
 
-        // load keys, warp-striped: item k of lane l in wave w is w*64*IPT + k*64 + l
+        // load, warp-striped: item k of lane l in wave w is w*64*IPT + k*64 + l
         K key[IPT];
+        V val[IPT];
         u32 rk[IPT];
         u32 dg[IPT];
 #pragma unroll
         for (int k = 0; k < IPT; k++) {
             const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-            key[k] = idx < n ? kin[start + idx] : (K)0;
+            if constexpr (GEN) {
+                const u32 x = (u32)(c * PART + idx);
+                key[k] = idx < n ? raw_key<K>(s, ckeys, x) : (K)0;
+                val[k] = (V)x;
+            } else {
+                key[k] = idx < n ? kin[start + idx] : (K)0;
+            }
+        }
+        if constexpr (!GEN) {
+            // payloads are only permuted: issue their loads now so they overlap the ranking
+#pragma unroll
+            for (int k = 0; k < IPT; k++) {
+                const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+                val[k] = idx < n ? vin[start + idx] : (V)0;
+            }
         }
         // per-wave stable ranking
 #pragma unroll
@@ -452,6 +480,7 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
             if (valid && before == 0) s_wh[w][d] = old + cnt;
             rk[k] = old + before;
             dg[k] = d;
+            if (next_hist && valid) atomicAdd(&s_nh[(u32)((key[k] >> (shift + RADIX_BITS)) & (RADIX - 1))], 1u);
         }
         __syncthreads();
         // digit totals, wave prefixes, local digit offsets
@@ -467,8 +496,8 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
         const u32 loff = block_excl_scan<u32>(tot, s_scan, all);
         s_loff[d] = loff;
         // product-wide offset of this digit in this partition
-        const u64 prefix = lookback(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
-        s_goff[d] = (i64)(C.bases[((i64)pass * C.nseg + q) * RADIX + d] + prefix) - (i64)loff;
+        const u64 prefix = lookback_batched(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
+        s_goff[d] = (i64)(s_base[d] + prefix) - (i64)loff;
         __syncthreads();
         // scatter keys into LDS in sorted order
 #pragma unroll
@@ -492,7 +521,7 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
 #pragma unroll
         for (int k = 0; k < IPT; k++) {
             const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-            if (idx < n) s_buf.v[rk[k]] = vin[start + idx];
+            if (idx < n) s_buf.v[rk[k]] = val[k];
         }
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += NTHREADS) {
@@ -500,30 +529,53 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
             if (o >= lo && o < hi) vout[o] = s_buf.v[i];
         }
         __syncthreads();
+        }
+    }
+    if (cur_q >= 0 && next_hist) {
+        __syncthreads();
+        hist_flush(C, s_nh, pass + 1, cur_q);
     }
 }
 
 // ---------------------------------------------------------------------------
 // k_reduce: sorted staging -> result.  A run of equal keys is summed by the
 // thread that owns its first element, left to right in staging order (for
-// FP64 that is the row-major (i, j) order), reading past the partition end
-// when the run continues.  Non-zero sums get their result position from a
-// workgroup scan plus a look-back over the product's earlier partitions; the
-// key is decompressed back to the packed exponent layout.
+// FP64 that is the row-major (i, j) order of the pp-matrix, as the sort is
+// stable and SEG_RAW items start in index order), continuing past the
+// thread's items and the partition end when the run does.  Non-zero sums get
+// their result position from a workgroup scan plus a look-back over the
+// product's earlier partitions; results are staged in LDS and written out
+// contiguously with the key decompressed to the packed exponent layout.
 // ---------------------------------------------------------------------------
-template <typename K, int RING>
-__global__ __launch_bounds__(NTHREADS) void k_reduce(Ctx C, const K *__restrict__ kin, const u64 *__restrict__ vin) {
-    __shared__ K s_k[PART];
-    __shared__ u64 s_v[PART];
+template <typename K, typename V, int RING>
+__device__ inline u64 item_value(const DevSeg &s, V v) {
+    if constexpr (sizeof(V) == 8) {
+        return (u64)v;
+    } else {
+        const u32 i = div32((u32)v, s.nb_div);
+        const u32 j = (u32)v - i * (u32)s.nb;
+        return ring_mul<RING>(s.fc[i], s.gc[j]);
+    }
+}
+
+template <typename K, typename V, int RING>
+__global__ __launch_bounds__(NTHREADS) void k_reduce(Ctx C, const K *__restrict__ kin, const V *__restrict__ vin) {
+    constexpr int PADN = PART + PART / 16;
+    __shared__ K s_k[PADN];
+    __shared__ u64 s_v[PADN];
     __shared__ u32 s_scan[NTHREADS / 64];
     __shared__ i64 s_p;
     __shared__ u64 s_base;
+    auto pad = [](int i) { return i + (i >> 4); };
     const i64 nparts = C.ppre[C.nseg];
+    const i64 tb = C.tb_sort;
     while (true) {
-        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_REDUCE], 1u);
+        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_REDUCE], 1u) * tb;
         __syncthreads();
-        const i64 p = s_p;
-        if (p >= nparts) break;
+        const i64 p0 = s_p;
+        if (p0 >= nparts) break;
+        __syncthreads();
+        for (i64 p = p0; p < min(p0 + tb, nparts); p++) {
         const int q = seg_search(C.ppre, C.nseg, p);
         const DevSeg &s = C.segs[q];
         const i64 first = C.ppre[q];
@@ -534,51 +586,89 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(Ctx C, const K *__restrict_
         const i64 send = seg0 + n_q;
         const int n = (int)min((i64)PART, n_q - c * PART);
         for (int i = threadIdx.x; i < n; i += NTHREADS) {
-            s_k[i] = kin[start + i];
-            s_v[i] = vin[start + i];
+            s_k[pad(i)] = kin[start + i];
+            s_v[pad(i)] = item_value<K, V, RING>(s, vin[start + i]);
         }
         const K prevk = c > 0 ? kin[start - 1] : (K)0;
         __syncthreads();
-        // each thread: items [t*IPT, t*IPT+IPT)
-        u32 mask = 0;
+        // thread t owns items [t*IPT, t*IPT+IPT); a run's head sums the run
         const int b0 = threadIdx.x * IPT;
+        u32 mask = 0;
+        K kprev = b0 == 0 ? prevk : s_k[pad(b0 - 1)];
+        bool have_prev = !(b0 == 0 && c == 0);
+        int open = -1;
+        u64 acc = 0;
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
             const int i = b0 + r;
-            if (i >= n) break;
-            const K key = s_k[i];
-            const bool head = (start + i == seg0) || key != (i == 0 ? prevk : s_k[i - 1]);
-            if (!head) continue;
-            u64 acc = s_v[i];
-            int j = i + 1;
-            while (j < n && s_k[j] == key) acc = ring_add<RING>(acc, s_v[j++]);
-            if (j == n) {
-                for (i64 g = start + j; g < send && kin[g] == key; g++) acc = ring_add<RING>(acc, vin[g]);
+            if (i < n) {
+                const K key = s_k[pad(i)];
+                const u64 v = s_v[pad(i)];
+                const bool head = !have_prev || key != kprev;
+                if (head) {
+                    if (open >= 0) {
+                        s_v[pad(b0 + open)] = acc;
+                        if (!ring_is_zero<RING>(acc)) mask |= 1u << open;
+                    }
+                    open = r;
+                    acc = v;
+                } else if (open >= 0) {
+                    acc = ring_add<RING>(acc, v);
+                }
+                kprev = key;
+                have_prev = true;
             }
-            if (!ring_is_zero<RING>(acc)) {
-                mask |= 1u << r;
-                s_v[i] = acc;  // only this thread reads a head's slot
+        }
+        if (open >= 0) {
+            // the last run may continue into the next threads' items and partitions
+            const K key = s_k[pad(b0 + open)];
+            int j = b0 + IPT;
+            while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
+            if (j >= n && n > 0) {
+                for (i64 g = start + n; g < send && kin[g] == key; g++)
+                    acc = ring_add<RING>(acc, item_value<K, V, RING>(s, vin[g]));
             }
+            s_v[pad(b0 + open)] = acc;
+            if (!ring_is_zero<RING>(acc)) mask |= 1u << open;
         }
         const u32 cnt = (u32)__popc(mask);
         u32 total;
         const u32 off = block_excl_scan<u32>(cnt, s_scan, total);
-        if (threadIdx.x == 0) s_base = lookback(C.look_red, 1, first, p, 200u, total, &C.counters[CNT_ERR_SPIN]);
-        __syncthreads();
-        const u64 base = s_base + off;
-        const VarParam *vp = C.vars + s.var_off;
-        u32 r2 = 0;
+        if (threadIdx.x < 64) {
+            const u64 pre = lookback_wave(C.look_red, first, p, 200u, total, &C.counters[CNT_ERR_SPIN]);
+            if (threadIdx.x == 0) s_base = pre;
+        }
+        // gather this thread's results, then stage them compacted in LDS
+        K ok[IPT];
+        u64 ov[IPT];
+#pragma unroll
         for (int r = 0; r < IPT; r++) {
-            if (!(mask & (1u << r))) continue;
-            const u64 pos = base + r2++;
+            ok[r] = s_k[pad(b0 + r < PART ? b0 + r : 0)];
+            ov[r] = s_v[pad(b0 + r < PART ? b0 + r : 0)];
+        }
+        __syncthreads();
+        u32 o = off;
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            if (mask & (1u << r)) {
+                s_k[o] = ok[r];
+                s_v[o] = ov[r];
+                o++;
+            }
+        }
+        __syncthreads();
+        const u64 base = s_base;
+        const VarParam *vp = C.vars + s.var_off;
+        for (int i = threadIdx.x; i < (int)total; i += NTHREADS) {
+            const u64 pos = base + i;
             if ((i64)pos < s.cap) {
-                const int i = b0 + r;
                 s.hk[pos] = decompress<K>(s_k[i], vp, C.nvars, s.lo_key);
                 s.hc[pos] = s_v[i];
             }
         }
-        if (c == C.dyn[q].nparts - 1 && threadIdx.x == 0) *s.n_out = (i64)(s_base + total);
+        if (c == C.dyn[q].nparts - 1 && threadIdx.x == 0) *s.n_out = (i64)(base + total);
         __syncthreads();
+        }
     }
 }
 
@@ -592,11 +682,14 @@ __global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
     __shared__ u32 s_scan[NTHREADS / 64];
     __shared__ i64 s_p;
     __shared__ u64 s_base;
+    const i64 tb = C.tb_cmp;
     while (true) {
-        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_COMPACT], 1u);
+        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_COMPACT], 1u) * tb;
         __syncthreads();
-        const i64 p = s_p;
-        if (p >= C.ndparts) break;
+        const i64 p0 = s_p;
+        if (p0 >= C.ndparts) break;
+        __syncthreads();
+        for (i64 p = p0; p < min(p0 + tb, C.ndparts); p++) {
         const i32 ds = seg_search(C.dpart_pre, C.ndseg, p);
         const int q = C.dseg[ds];
         const DevSeg &s = C.segs[q];
@@ -619,7 +712,10 @@ __global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
         const u32 cnt = (u32)__popc(mask);
         u32 total;
         const u32 off = block_excl_scan<u32>(cnt, s_scan, total);
-        if (threadIdx.x == 0) s_base = lookback(C.look_cmp, 1, first, p, 201u, total, &C.counters[CNT_ERR_SPIN]);
+        if (threadIdx.x < 64) {
+            const u64 pre = lookback_wave(C.look_cmp, first, p, 201u, total, &C.counters[CNT_ERR_SPIN]);
+            if (threadIdx.x == 0) s_base = pre;
+        }
         __syncthreads();
         const u64 base = s_base + off;
         const VarParam *vp = C.vars + s.var_off;
@@ -635,6 +731,7 @@ __global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
         }
         if (c == nparts - 1 && threadIdx.x == 0) *s.n_out = (i64)(s_base + total);
         __syncthreads();
+        }
     }
 }
 
@@ -749,6 +846,18 @@ int profile_read(int i, char *name, int cap, double *total_ms, int64_t *launches
     return n;
 }
 
+static int device_cus_cached() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
 static inline int grid_for(int64_t work, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(work, cap)); }
 
 hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int ring, u64 *out, u32 *flags,
@@ -768,6 +877,36 @@ static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid) {
     }
 }
 
+template <typename K, typename V, int RING>
+static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
+    {
+        ProfScope ps("seg_prepare", st);
+        hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
+    }
+    const int g = grid_for(P.nparts_bound, cus * 3);
+    K *ka = (K *)C.stA_k, *kb = (K *)C.stB_k;
+    V *va = (V *)C.stA_v, *vb = (V *)C.stB_v;
+    if (P.raw && P.passes > 0) {
+        {
+            ProfScope ps("hist_raw", st);
+            hipLaunchKernelGGL((k_hist_raw<K>), dim3(grid_for(P.nparts_bound, cus * 8)), dim3(NTHREADS), 0, st, C);
+        }
+        ProfScope ps("onesweep_gen", st);
+        hipLaunchKernelGGL((k_onesweep<K, V, true>), dim3(g), dim3(NTHREADS), 0, st, C, 0, ka, va, kb, vb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    for (int pass = (P.raw ? 1 : 0); pass < P.passes; pass++) {
+        ProfScope ps("onesweep", st);
+        hipLaunchKernelGGL((k_onesweep<K, V, false>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    ProfScope ps("reduce", st);
+    hipLaunchKernelGGL((k_reduce<K, V, RING>), dim3(grid_for(P.nparts_bound, cus * 2)), dim3(NTHREADS), 0, st, C,
+                       ka, va);
+}
+
 template <typename K, int RING>
 static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
     if (P.nck > 0) {
@@ -778,28 +917,12 @@ static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
     if (P.ntiles > 0) {
         if constexpr (RING != RING_F64) launch_tile<K, RING>(P, C, st, grid_for(P.ntiles, cus * 8));
     }
-    if (P.nraw > 0) {
-        ProfScope ps("expand_raw", st);
-        hipLaunchKernelGGL((k_expand_raw<K, RING>), dim3(grid_for(P.nraw, cus * 8)), dim3(NTHREADS), 0, st, C);
-    }
     if (P.nsparse > 0) {
-        {
-            ProfScope ps("seg_prepare", st);
-            hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
-            if (P.passes > 0) hipLaunchKernelGGL(k_seg_bases, dim3(P.nseg), dim3(RADIX), 0, st, C);
+        if (P.raw) {
+            launch_sort_reduce<K, u32, RING>(P, C, st, cus);
+        } else {
+            if constexpr (RING != RING_F64) launch_sort_reduce<K, u64, RING>(P, C, st, cus);
         }
-        K *ka = (K *)C.stA_k, *kb = (K *)C.stB_k;
-        u64 *va = C.stA_v, *vb = C.stB_v;
-        const int g = grid_for(P.nparts_bound, cus * 3);
-        for (int pass = 0; pass < P.passes; pass++) {
-            ProfScope ps("onesweep", st);
-            hipLaunchKernelGGL((k_onesweep<K>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
-            std::swap(ka, kb);
-            std::swap(va, vb);
-        }
-        ProfScope ps("reduce", st);
-        hipLaunchKernelGGL((k_reduce<K, RING>), dim3(grid_for(P.nparts_bound, cus * 3)), dim3(NTHREADS), 0, st, C,
-                           ka, va);
     } else if (P.nseg > 0) {
         // products without a sort still need n_out = 0 when an operand is empty
         hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
@@ -832,6 +955,11 @@ hipError_t launch_pipeline(const Plan &P, const Ctx &C, hipStream_t st, int cus)
     return hipGetLastError();
 }
 
+static i32 ticket_batch(int64_t work, int grid) {
+    int64_t b = work / (2 * (int64_t)std::max(grid, 1));
+    return (i32)std::max<int64_t>(1, std::min<int64_t>(b, 16));
+}
+
 Ctx make_ctx(const Plan &P, void *ws) {
     char *b = (char *)ws;
     Ctx C;
@@ -840,33 +968,37 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.vars = (VarParam *)(b + P.o_vars);
     C.tile_pre = (const i64 *)(b + P.o_tile_pre);
     C.tile_seg = (const i32 *)(b + P.o_tile_seg);
-    C.raw_pre = (const i64 *)(b + P.o_raw_pre);
-    C.raw_seg = (const i32 *)(b + P.o_raw_seg);
     C.dpart_pre = (const i64 *)(b + P.o_dpart_pre);
     C.dseg = (const i32 *)(b + P.o_dseg);
     C.ppre = (i64 *)(b + P.o_ppre);
     C.ck = b + P.o_ck;
     C.stA_k = b + P.o_stAk;
-    C.stA_v = (u64 *)(b + P.o_stAv);
+    C.stA_v = b + P.o_stAv;
     C.stB_k = b + P.o_stBk;
-    C.stB_v = (u64 *)(b + P.o_stBv);
+    C.stB_v = b + P.o_stBv;
     C.box = (u64 *)(b + P.o_box);
     C.hist = (unsigned long long *)(b + P.o_hist);
-    C.bases = (u64 *)(b + P.o_bases);
     C.look = (u64 *)(b + P.o_look);
     C.look_red = (u64 *)(b + P.o_look_red);
     C.look_cmp = (u64 *)(b + P.o_look_cmp);
+    C.look_tile = (u64 *)(b + P.o_look_tile);
     C.counters = (u32 *)(b + P.o_counters);
     C.nseg = P.nseg;
     C.ntseg = (i32)P.tile_seg.size();
-    C.nrseg = (i32)P.raw_seg.size();
     C.ndseg = (i32)P.dseg.size();
     C.nvars = P.nvars;
     C.bits = P.bits;
     C.passes = P.passes;
     C.ring = P.ring;
     C.ntiles = P.ntiles;
-    C.nraw = P.nraw;
+    C.raw = P.raw;
+    const int cus = device_cus_cached();
+    // A ticket may cover several consecutive work items only where no
+    // look-back follows: a batch's first item would otherwise wait for the
+    // previous batch's last one and serialise the queue.
+    C.tb_tile = P.raw ? ticket_batch(P.ntiles, cus * 8) : 1;
+    C.tb_sort = 1;
+    C.tb_cmp = 1;
     C.ndparts = P.ndparts;
     return C;
 }

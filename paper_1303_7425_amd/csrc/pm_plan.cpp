@@ -73,6 +73,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             vp.minf = fmin[v];
             vp.ming = gmin[v];
             vp.range = (uint64_t)r;  // 0 encodes 2^64 (one full-width variable)
+            if (r <= 0xFFFFFFFFull) vp.rdiv = make_div32((uint32_t)r);
             lo_key += (fmin[v] + gmin[v]) << vp.shift;
             if (!big) {
                 b *= r;
@@ -99,8 +100,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         if (can_dense) {
             d.mode = SEG_DENSE;
         } else {
-            const bool full = box[q] >= ((unsigned __int128)1 << 64);
-            d.mode = (ring == RING_F64 || tune.force_raw || full) ? SEG_RAW : SEG_COMBINE;
+            d.mode = SEG_RAW;  // decided for the whole launch below
             int kb = bitlen128(box[q] - 1);
             max_bits = std::max(max_bits, kb);
         }
@@ -108,6 +108,25 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     }
     P.ksize = need_u64 ? 8 : 4;
     P.passes = (max_bits + RADIX_BITS - 1) / RADIX_BITS;
+
+    // one sort mode per launch: pair indices (products regenerated in the
+    // reduction, FP64 summed in row-major order) or LDS-combined coefficients
+    // (exact rings only; needs a free hash sentinel, i.e. box < 2^(8*ksize)).
+    bool idx_fits = true, sentinel_ok = true;
+    for (int q = 0; q < S; q++) {
+        if (P.segs[q].mode != SEG_RAW) continue;
+        if ((unsigned __int128)P.segs[q].na * P.segs[q].nb > 0xFFFFFFFFull) idx_fits = false;
+        if (box[q] >= ((unsigned __int128)1 << 64)) sentinel_ok = false;
+    }
+    bool combine = ring != RING_F64 && sentinel_ok && (tune.combine == 1 || !idx_fits);
+    if (!combine && !idx_fits) return PM_ENOMEM;  // FP64 product of more than 2^32 - 1 term pairs
+    P.raw = combine ? 0 : 1;
+    P.vsize = combine ? 8 : 4;
+    for (int q = 0; q < S; q++)
+        if (P.segs[q].mode == SEG_RAW && combine) P.segs[q].mode = SEG_COMBINE;
+    bool any_sparse = false;
+    for (int q = 0; q < S; q++) any_sparse |= P.segs[q].mode == SEG_RAW || P.segs[q].mode == SEG_COMBINE;
+    if (P.raw && any_sparse && P.passes == 0) P.passes = 1;  // pass 0 also generates the items
 
     // tile shape: explicit, or the largest one that still gives >= 512 tiles
     // over the tiled products (at least two per compute unit); the sparse
@@ -119,7 +138,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         if (d.mode == SEG_COMBINE || d.mode == SEG_DENSE) tiled_pairs += d.na * d.nb;
         if (d.mode == SEG_COMBINE) any_combine = true;
     }
-    if (tune.tile_cfg >= 0 && tune.tile_cfg < N_TILE_CFGS) {
+    if (tune.tile_cfg >= 0 && tune.tile_cfg < N_TILE_CFGS && (!any_combine || tile_cfg_combines(tune.tile_cfg))) {
         P.tile_cfg = tune.tile_cfg;
     } else if (any_combine) {
         P.tile_cfg = 0;
@@ -136,7 +155,6 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
 
     // queues and offsets
     P.tile_pre.push_back(0);
-    P.raw_pre.push_back(0);
     P.dpart_pre.push_back(0);
     P.cpre.push_back(0);
     int64_t nstage = 0, nbox = 0, nck = 0;
@@ -155,12 +173,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             P.tile_seg.push_back(q);
             P.tile_pre.push_back(P.tile_pre.back() + tmn * tnn);
         }
-        if (d.mode == SEG_RAW) {
-            d.raw_chunks = (d.nb + 4095) / 4096;
-            d.raw_first = P.raw_pre.back();
-            P.raw_seg.push_back(q);
-            P.raw_pre.push_back(P.raw_pre.back() + d.na * d.raw_chunks);
-        }
+        if (d.mode == SEG_RAW) d.nb_div = make_div32((uint32_t)d.nb);
         if (d.mode == SEG_COMBINE || d.mode == SEG_RAW) {
             d.stage_base = nstage;
             d.stage_bound = d.na * d.nb;
@@ -179,7 +192,6 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         }
     }
     P.ntiles = P.tile_pre.back();
-    P.nraw = P.raw_pre.back();
     P.ndparts = P.dpart_pre.back();
     P.nstage = nstage;
     P.nbox = nbox;
@@ -201,8 +213,6 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_vars = take(sizeof(VarParam) * S * nvars);
     P.o_tile_pre = take(8 * P.tile_pre.size());
     P.o_tile_seg = take(4 * std::max<size_t>(1, P.tile_seg.size()));
-    P.o_raw_pre = take(8 * P.raw_pre.size());
-    P.o_raw_seg = take(4 * std::max<size_t>(1, P.raw_seg.size()));
     P.o_dpart_pre = take(8 * P.dpart_pre.size());
     P.o_dseg = take(4 * std::max<size_t>(1, P.dseg.size()));
     P.o_cpre = take(8 * P.cpre.size());
@@ -215,16 +225,16 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_look = take((size_t)8 * RADIX * std::max<int64_t>(1, P.nparts_bound));
     P.o_look_red = take((size_t)8 * std::max<int64_t>(1, P.nparts_bound));
     P.o_look_cmp = take((size_t)8 * std::max<int64_t>(1, P.ndparts));
+    P.o_look_tile = take((size_t)8 * std::max<int64_t>(1, P.ntiles));
     P.o_box = take((size_t)8 * std::max<int64_t>(1, nbox));
     P.r_zero.off = zero0;
     P.r_zero.bytes = off - zero0;
     P.o_ppre = take((size_t)8 * (S + 1));
-    P.o_bases = take((size_t)8 * std::max(1, P.passes) * S * RADIX);
     P.o_ck = take((size_t)P.ksize * std::max<int64_t>(1, nck));
     P.o_stAk = take((size_t)P.ksize * std::max<int64_t>(1, nstage));
-    P.o_stAv = take((size_t)8 * std::max<int64_t>(1, nstage));
+    P.o_stAv = take((size_t)P.vsize * std::max<int64_t>(1, nstage));
     P.o_stBk = take((size_t)P.ksize * std::max<int64_t>(1, nstage));
-    P.o_stBv = take((size_t)8 * std::max<int64_t>(1, nstage));
+    P.o_stBv = take((size_t)P.vsize * std::max<int64_t>(1, nstage));
     P.total = off;
     return PM_OK;
 }

@@ -17,13 +17,16 @@ struct TileCfg {
     int tm, tn, hb;
 };
 
-// Tile shapes the kernels are instantiated for.
+// Tile shapes the kernels are instantiated for.  The sparse combine needs a
+// table of at least twice the tile's products (so a free slot always exists);
+// dense tiles may saturate their table and fall back to the box.
 constexpr TileCfg TILE_CFGS[] = {{32, 64, 12}, {64, 64, 12}, {128, 128, 12}};
+inline bool tile_cfg_combines(int c) { return 2 * TILE_CFGS[c].tm * TILE_CFGS[c].tn <= (1 << TILE_CFGS[c].hb); }
 constexpr int N_TILE_CFGS = 3;
 
 struct Tuning {
     int tile_cfg = -1;       // -1: choose automatically
-    int force_raw = 0;       // stage every product pair (no LDS combine) for exact rings
+    int combine = -1;        // exact rings: 1 LDS tile combine before the sort, 0 pair-index sort, -1 auto
     int allow_dense = 1;     // permit the degree-box path
     double dense_ratio = 2;  // dense when box * dense_ratio <= na * nb
     int64_t dense_max_cells = int64_t(1) << 27;
@@ -41,17 +44,18 @@ struct Plan {
     std::vector<DevSeg> segs;
     std::vector<VarParam> vars;
     std::vector<int64_t> bound;     // result-size bound per product
-    std::vector<int64_t> tile_pre, raw_pre, dpart_pre, cpre;
-    std::vector<int32_t> tile_seg, raw_seg, dseg;
-    int64_t ntiles = 0, nraw = 0, ndparts = 0, nparts_bound = 0;
+    std::vector<int64_t> tile_pre, dpart_pre, cpre;
+    std::vector<int32_t> tile_seg, dseg;
+    int64_t ntiles = 0, ndparts = 0, nparts_bound = 0;
+    int raw = 1;        // sparse products sort (key, pair index); else (key, coefficient)
+    int vsize = 4;      // payload bytes of a sort item
     int64_t nstage = 0, nbox = 0, nck = 0;
     int nsparse = 0, ndense = 0;
     // workspace layout
     Region r_stats, r_flags, r_desc, r_zero;
-    size_t o_segs = 0, o_vars = 0, o_tile_pre = 0, o_tile_seg = 0, o_raw_pre = 0, o_raw_seg = 0, o_dpart_pre = 0,
-           o_dseg = 0, o_cpre = 0;
-    size_t o_dyn = 0, o_counters = 0, o_hist = 0, o_look = 0, o_look_red = 0, o_look_cmp = 0, o_box = 0;
-    size_t o_ppre = 0, o_bases = 0, o_ck = 0, o_stAk = 0, o_stAv = 0, o_stBk = 0, o_stBv = 0;
+    size_t o_segs = 0, o_vars = 0, o_tile_pre = 0, o_tile_seg = 0, o_dpart_pre = 0, o_dseg = 0, o_cpre = 0;
+    size_t o_dyn = 0, o_counters = 0, o_hist = 0, o_look = 0, o_look_red = 0, o_look_cmp = 0, o_look_tile = 0, o_box = 0;
+    size_t o_ppre = 0, o_ck = 0, o_stAk = 0, o_stAv = 0, o_stBk = 0, o_stBv = 0;
     size_t total = 0;
 };
 

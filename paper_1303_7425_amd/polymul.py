@@ -71,7 +71,7 @@ def lib():
         L.pm_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.pm_last_call_status.argtypes = [vp]
         L.pm_last_call_info.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                        i64p]
+                                        ctypes.POINTER(ctypes.c_int32), i64p]
         L.pm_profile_enable.argtypes = [ctypes.c_int32]
         L.pm_profile_read.argtypes = [ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_double), i64p]
@@ -298,12 +298,13 @@ def last_call_status(stream=None):
 
 
 def last_call_info(stream=None):
-    """(staged pairs, radix passes, key bytes, degree-box cells) of the last call."""
+    """dict(staged, passes, key_bytes, payload_bytes, box_cells) of the last call."""
     sp, bc = ctypes.c_int64(0), ctypes.c_int64(0)
-    ps, kb = ctypes.c_int32(0), ctypes.c_int32(0)
+    ps, kb, vb = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     _check(lib().pm_last_call_info(_stream_ptr(stream), ctypes.byref(sp), ctypes.byref(ps), ctypes.byref(kb),
-                                   ctypes.byref(bc)), "pm_last_call_info")
-    return int(sp.value), int(ps.value), int(kb.value), int(bc.value)
+                                   ctypes.byref(vb), ctypes.byref(bc)), "pm_last_call_info")
+    return {"staged": int(sp.value), "passes": int(ps.value), "key_bytes": int(kb.value),
+            "payload_bytes": int(vb.value), "box_cells": int(bc.value)}
 
 
 def profile_enable(on: bool):
@@ -322,8 +323,10 @@ def profile_read():
     return out
 
 
-def set_tuning(tile_cfg: int = -1, force_raw: bool = False, allow_dense: bool = True):
-    _check(lib().pm_set_tuning(tile_cfg, int(force_raw), int(allow_dense)), "pm_set_tuning")
+def set_tuning(tile_cfg: int = -1, combine: int = -1, allow_dense: bool = True):
+    """Autotuner knobs (results never depend on them): tile shape index,
+    combine (-1 auto, 0 pair-index sort, 1 LDS tile combine), dense path on/off."""
+    _check(lib().pm_set_tuning(tile_cfg, int(combine), int(allow_dense)), "pm_set_tuning")
 
 
 def plan_from_stats(layout, na, nb, stats):

@@ -68,9 +68,9 @@ def check(f, g, tag=""):
 @pytest.fixture(autouse=True)
 def default_tuning():
     pm = _pm()
-    pm.set_tuning(-1, False, True)
+    pm.set_tuning(-1, -1, True)
     yield
-    pm.set_tuning(-1, False, True)
+    pm.set_tuning(-1, -1, True)
 
 
 # ------------------------------------------------------------- small configs
@@ -104,17 +104,21 @@ def test_random_6var_ragged(ring, na, nb):
     check(f, g, f"rand {na}x{nb}")
 
 
-@pytest.mark.parametrize("mode", ["auto", "raw", "nodense", "tile1", "tile2"])
+@pytest.mark.parametrize("mode", ["auto", "pairs", "combine", "nodense", "nodense_combine", "tile1", "tile2"])
 def test_tuning_modes_same_result(mode):
     pm = _pm()
-    if mode == "raw":
-        pm.set_tuning(-1, True, True)
+    if mode == "pairs":
+        pm.set_tuning(-1, 0, True)
+    elif mode == "combine":
+        pm.set_tuning(-1, 1, True)
     elif mode == "nodense":
-        pm.set_tuning(-1, False, False)
+        pm.set_tuning(-1, 0, False)
+    elif mode == "nodense_combine":
+        pm.set_tuning(-1, 1, False)
     elif mode == "tile1":
-        pm.set_tuning(1, False, True)
+        pm.set_tuning(1, -1, True)
     elif mode == "tile2":
-        pm.set_tuning(2, False, True)
+        pm.set_tuning(2, -1, True)
     for n in (5, 9):
         check(*W.config2(n), f"dense n={n} {mode}")
     check(W.sparse_power(5, "f", 12, "modp"), W.sparse_power(5, "g", 12, "modp"), f"sparse {mode}")
@@ -261,8 +265,8 @@ def test_config3_full(ring):
     check(f, g, f"cfg3 {ring}")
 
 
-def test_config3_modp_sparse_path_forced_raw():
+def test_config3_modp_lds_combine():
     pm = _pm()
-    pm.set_tuning(-1, True, True)
+    pm.set_tuning(-1, 1, True)
     f, g = W.config3("modp")
-    check(f, g, "cfg3 raw")
+    check(f, g, "cfg3 combine")
