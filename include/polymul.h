@@ -125,6 +125,23 @@ int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, cons
                  void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
+ * Prepared batch: validate and plan `count` products once, upload their
+ * descriptors into `workspace`, and capture the whole device pipeline (zeroing,
+ * key compression, tile / pair work queues, radix passes, reduction, dense
+ * compaction) in one HIP graph.  pm_batch_launch replays that graph on
+ * `stream`: one graph launch runs every product of the batch.  Operands,
+ * results and workspace stay bound to the batch; operand contents may change
+ * between launches only if term counts, strict ordering and per-variable
+ * exponent ranges stay within what was validated (prepare again otherwise).
+ * Returns NULL in *out on error.
+ */
+typedef struct pm_batch pm_batch;
+int pm_batch_prepare(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
+                     void *workspace, int64_t workspace_bytes, void *stream, pm_batch **out);
+int pm_batch_launch(pm_batch *b, void *stream);
+void pm_batch_destroy(pm_batch *b);
+
+/*
  * Serving loop (continuous batching).  The server owns one device arena of
  * `hbm_budget_bytes`, allocated once at create, and a scheduler thread.  A
  * submitted product is admitted when its bound-sized workspace fits the free
@@ -204,6 +221,21 @@ int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int3
  */
 int pm_profile_enable(int32_t enable);
 int pm_profile_read(int32_t i, char *name, int32_t name_cap, double *total_ms, int64_t *launches);
+
+/*
+ * Autotuner.  Runs h = f * g once per candidate setting (LDS tile combine on
+ * or off for exact rings; tile shape for the degree-box path), times each with
+ * HIP events on `stream`, and remembers the fastest for the product's size
+ * class (ring, path, floor(log2(term pairs))).  Later calls with automatic
+ * settings (pm_set_tuning(-1, -1, ...), the default) use the remembered choice
+ * for their largest product's class.  A setting whose workspace exceeds
+ * `workspace_bytes` is skipped.  *tile_cfg and *combine (may be NULL) receive
+ * the choice.  Results never depend on it.  Synchronises `stream`.
+ */
+int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
+                int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine);
+/* Forget every autotuner choice. */
+void pm_autotune_reset(void);
 
 /* Static message for an error code. */
 const char *pm_strerror(int code);

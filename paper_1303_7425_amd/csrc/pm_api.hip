@@ -167,13 +167,7 @@ int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cp
 
 // Upload the descriptor block of plan P (output pointers filled) and enqueue
 // the pipeline.
-int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st) {
-    for (int q = 0; q < P.nseg; q++) {
-        P.segs[q].hk = h[q].keys;
-        P.segs[q].hc = (u64 *)h[q].coefs;
-        P.segs[q].n_out = h[q].n_out;
-        P.segs[q].cap = h[q].capacity;
-    }
+int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st) {
     int rc = hs.reserve(P.r_desc.bytes);
     if (rc) return rc;
     char *pin = (char *)hs.pin;
@@ -192,6 +186,19 @@ int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStr
         return PM_EDEVICE;
     }
     hs.used = true;
+    return PM_OK;
+}
+
+int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st) {
+    for (int q = 0; q < P.nseg; q++) {
+        P.segs[q].hk = h[q].keys;
+        P.segs[q].hc = (u64 *)h[q].coefs;
+        P.segs[q].n_out = h[q].n_out;
+        P.segs[q].cap = h[q].capacity;
+    }
+    int rc = upload_descriptors(hs, P, ws, st);
+    if (rc) return rc;
+    hipError_t e;
     g_last_counters = (char *)ws + P.o_counters;
     g_last.dyn = (char *)ws + P.o_dyn;
     g_last.nseg = P.nseg;
@@ -287,6 +294,161 @@ int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, cons
     return mul_impl(g_stage, layout, count, f, g, h, workspace, workspace_bytes, (hipStream_t)stream, g_tune,
                     nullptr);
 }
+
+}  // extern "C"
+
+struct pm_batch {
+    pm::Plan plan;
+    void *ws = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int pm_batch_prepare(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
+                     void *workspace, int64_t workspace_bytes, void *stream, pm_batch **out) {
+    if (!out) return PM_EINVAL;
+    *out = nullptr;
+    int rc = check_args(layout, count, f, g, h);
+    if (rc) return rc;
+    if (count < 1 || !h) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need0 = stats_region_bytes((int)count, (int)layout->nvars) + sizeof(DevSeg) * count;
+    if (!workspace || workspace_bytes < (int64_t)need0) return PM_ENOMEM;
+    pm_batch *b = new pm_batch();
+    rc = stats_and_plan(g_stage, layout, count, f, g, workspace, st, g_tune, b->plan);
+    if (!rc && (int64_t)b->plan.total > workspace_bytes) rc = PM_ENOMEM;
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    Plan &P = b->plan;
+    b->ws = workspace;
+    for (int q = 0; q < P.nseg; q++) {
+        P.segs[q].hk = h[q].keys;
+        P.segs[q].hc = (u64 *)h[q].coefs;
+        P.segs[q].n_out = h[q].n_out;
+        P.segs[q].cap = h[q].capacity;
+    }
+    // descriptors: upload once and wait, the graph only reads them
+    rc = upload_descriptors(g_stage, P, workspace, st);
+    hipError_t e = hipSuccess;
+    if (!rc) e = hipStreamSynchronize(st);
+    if (!rc && e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (!rc && e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (!rc && e == hipSuccess) {
+        Ctx C = make_ctx(P, workspace);
+        hipError_t le = launch_pipeline(P, C, b->cap, device_cus());
+        e = hipStreamEndCapture(b->cap, &b->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (!rc && e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (!rc && e != hipSuccess) {
+        set_error("graph capture", e);
+        rc = PM_EDEVICE;
+    }
+    if (rc) {
+        pm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PM_OK;
+}
+
+int pm_batch_launch(pm_batch *b, void *stream) {
+    if (!b || !b->exec) return PM_EINVAL;
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("hipGraphLaunch", e);
+        return PM_EDEVICE;
+    }
+    g_last_counters = (char *)b->ws + b->plan.o_counters;
+    g_last.dyn = (char *)b->ws + b->plan.o_dyn;
+    g_last.nseg = b->plan.nseg;
+    g_last.passes = b->plan.passes;
+    g_last.ksize = b->plan.ksize;
+    g_last.vsize = b->plan.vsize;
+    g_last.box = b->plan.nbox;
+    return PM_OK;
+}
+
+void pm_batch_destroy(pm_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
+                int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine) {
+    int rc = check_args(layout, 1, f, g, h);
+    if (rc) return rc;
+    if (!h) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t st = (hipStream_t)stream;
+    // which path does this product take?
+    Plan P0;
+    Tuning base = g_tune;
+    base.tile_cfg = -1;
+    base.combine = -1;
+    rc = mul_impl(g_stage, layout, 1, f, g, h, workspace, workspace_bytes, st, base, &P0);
+    if (rc) return rc;
+    if (P0.nseg < 1 || P0.segs[0].mode == SEG_EMPTY) return PM_OK;
+    const bool dense = P0.segs[0].mode == SEG_DENSE;
+    std::vector<std::pair<int, int>> cands;  // (tile_cfg, combine)
+    if (dense) {
+        for (int t = 0; t < N_TILE_CFGS; t++) cands.push_back({t, 0});
+    } else if (layout->ring != PM_F64) {
+        cands.push_back({-1, 0});
+        cands.push_back({0, 1});
+    } else {
+        cands.push_back({-1, 0});
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PM_EDEVICE;
+    float best = 1e30f;
+    std::pair<int, int> choice = cands[0];
+    for (auto &cd : cands) {
+        Tuning t = base;
+        t.tile_cfg = cd.first;
+        t.combine = cd.second;
+        rc = mul_impl(g_stage, layout, 1, f, g, h, workspace, workspace_bytes, st, t, nullptr);  // warm-up
+        if (rc == PM_ENOMEM) {  // this setting needs more workspace than given: not a candidate
+            rc = PM_OK;
+            continue;
+        }
+        if (rc) break;
+        float total = 0;
+        for (int rep = 0; rep < 2 && !rc; rep++) {
+            (void)hipEventRecord(e0, st);
+            rc = mul_impl(g_stage, layout, 1, f, g, h, workspace, workspace_bytes, st, t, nullptr);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            total += ms;
+        }
+        if (rc) break;
+        if (total < best) {
+            best = total;
+            choice = cd;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    const uint64_t pairs = (uint64_t)f->n * (uint64_t)g->n;
+    tune_store(TuneClass{layout->ring, dense ? 1 : 0, log2_floor(pairs)}, choice.first, choice.second);
+    if (tile_cfg) *tile_cfg = choice.first;
+    if (combine) *combine = choice.second;
+    return PM_OK;
+}
+
+void pm_autotune_reset(void) { tune_reset(); }
 
 int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na, const int64_t *nb,
                        const uint64_t *stats, int64_t *max_terms, int64_t *workspace_bytes) {

@@ -777,6 +777,8 @@ struct Profiler {
     int begin(const char *name, hipStream_t st) {
         std::lock_guard<std::mutex> lk(mu);
         if (!on) return -1;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return -1;
         int id = -1;
         for (size_t i = 0; i < names.size(); i++)
             if (names[i] == name) id = (int)i;

@@ -2,10 +2,43 @@
 #include "pm_plan.hpp"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "../../include/polymul.h"
 
 namespace pm {
+
+static std::mutex g_tune_mu;
+static std::map<TuneClass, std::pair<int, int>> g_tune_cache;
+
+bool tune_lookup(const TuneClass &c, int &tile_cfg, int &combine) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(c);
+    if (it == g_tune_cache.end()) return false;
+    tile_cfg = it->second.first;
+    combine = it->second.second;
+    return true;
+}
+
+void tune_store(const TuneClass &c, int tile_cfg, int combine) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[c] = {tile_cfg, combine};
+}
+
+void tune_reset() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+}
+
+int log2_floor(uint64_t x) {
+    int b = -1;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -23,7 +56,7 @@ static int bitlen128(unsigned __int128 x) {
 }
 
 int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, const uint64_t *stats,
-               const uint32_t *flags, const Tuning &tune, Plan &P) {
+               const uint32_t *flags, const Tuning &tune_in, Plan &P) {
     const int S = (int)in.size();
     P = Plan();
     P.nseg = S;
@@ -95,8 +128,8 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         const unsigned __int128 bnd = std::min(prod, box[q]);
         P.bound[q] = (int64_t)bnd;
         // path
-        const bool can_dense = tune.allow_dense && ring != RING_F64 && box[q] <= (unsigned __int128)tune.dense_max_cells &&
-                               (double)box[q] * tune.dense_ratio <= (double)prod;
+        const bool can_dense = tune_in.allow_dense && ring != RING_F64 && box[q] <= (unsigned __int128)tune_in.dense_max_cells &&
+                               (double)box[q] * tune_in.dense_ratio <= (double)prod;
         if (can_dense) {
             d.mode = SEG_DENSE;
         } else {
@@ -108,6 +141,28 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     }
     P.ksize = need_u64 ? 8 : 4;
     P.passes = (max_bits + RADIX_BITS - 1) / RADIX_BITS;
+
+    // automatic settings: the autotuner's choice for the largest product's class
+    Tuning tune = tune_in;
+    {
+        int big = -1;
+        unsigned __int128 bigp = 0;
+        for (int q = 0; q < S; q++) {
+            const unsigned __int128 pr = (unsigned __int128)P.segs[q].na * P.segs[q].nb;
+            if (P.segs[q].mode != SEG_EMPTY && pr > bigp) {
+                bigp = pr;
+                big = q;
+            }
+        }
+        if (big >= 0) {
+            TuneClass tc{ring, P.segs[big].mode == SEG_DENSE ? 1 : 0, log2_floor((uint64_t)bigp)};
+            int tcfg, comb;
+            if (tune_lookup(tc, tcfg, comb)) {
+                if (tune.tile_cfg < 0) tune.tile_cfg = tcfg;
+                if (tune.combine < 0) tune.combine = comb;
+            }
+        }
+    }
 
     // one sort mode per launch: pair indices (products regenerated in the
     // reduction, FP64 summed in row-major order) or LDS-combined coefficients

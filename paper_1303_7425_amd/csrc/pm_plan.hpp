@@ -32,6 +32,20 @@ struct Tuning {
     int64_t dense_max_cells = int64_t(1) << 27;
 };
 
+// Autotuner cache: size class -> (tile_cfg, combine).  Thread-safe.
+struct TuneClass {
+    int ring, dense, log2pairs;
+    bool operator<(const TuneClass &o) const {
+        if (ring != o.ring) return ring < o.ring;
+        if (dense != o.dense) return dense < o.dense;
+        return log2pairs < o.log2pairs;
+    }
+};
+bool tune_lookup(const TuneClass &c, int &tile_cfg, int &combine);
+void tune_store(const TuneClass &c, int tile_cfg, int combine);
+void tune_reset();
+int log2_floor(uint64_t x);
+
 struct Region {
     size_t off = 0, bytes = 0;
 };

@@ -79,6 +79,14 @@ def lib():
         L.pm_strerror.argtypes = [ctypes.c_int]
         L.pm_last_error.restype = ctypes.c_char_p
         L.pm_version.restype = ctypes.c_char_p
+        L.pm_batch_prepare.argtypes = [ctypes.POINTER(pm_layout), i64, ctypes.POINTER(pm_cpoly),
+                                       ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_poly), vp, i64, vp,
+                                       ctypes.POINTER(vp)]
+        L.pm_batch_launch.argtypes = [vp, vp]
+        L.pm_batch_destroy.argtypes = [vp]
+        L.pm_autotune.argtypes = [ctypes.POINTER(pm_layout), ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_cpoly),
+                                  ctypes.POINTER(pm_poly), vp, i64, vp, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]
         if hasattr(L, "pm_server_create"):
             L.pm_server_create.restype = vp
             L.pm_server_create.argtypes = [i64, ctypes.c_int32]
@@ -265,10 +273,30 @@ class BatchCall:
         self.h = (pm_poly * self.count)(*hs)
         self.ws = (workspace or Workspace()).get(self.ws_bytes)
 
+        self.graph = None
+
     def run(self):
+        """One pm_mul_batch call (validation round trip + launches)."""
         _check(lib().pm_mul_batch(ctypes.byref(self.L), self.count, self.cf, self.cg, self.h,
                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream_ptr(self.stream)),
                "pm_mul_batch")
+
+    def prepare_graph(self):
+        """Validate once and capture the batch's whole pipeline in a HIP graph."""
+        b = ctypes.c_void_p(None)
+        _check(lib().pm_batch_prepare(ctypes.byref(self.L), self.count, self.cf, self.cg, self.h,
+                                      ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                      _stream_ptr(self.stream), ctypes.byref(b)), "pm_batch_prepare")
+        self.graph = b
+
+    def launch_graph(self):
+        _check(lib().pm_batch_launch(self.graph, _stream_ptr(self.stream)), "pm_batch_launch")
+
+    def __del__(self):
+        g = getattr(self, "graph", None)
+        if g is not None and _lib is not None:
+            _lib.pm_batch_destroy(g)
+            self.graph = None
 
     def results(self):
         """List of (keys u64, coefs) numpy arrays, after the stream completes."""
@@ -341,3 +369,66 @@ def plan_from_stats(layout, na, nb, stats):
     rc = lib().pm_plan_from_stats(ctypes.byref(L), count, na_a, nb_a,
                                   st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), mt, ctypes.byref(wb))
     return rc, [int(mt[i]) for i in range(count)], int(wb.value)
+
+
+def autotune(layout, f: DevPoly, g: DevPoly, workspace: Workspace | None = None, stream=None):
+    """Time the candidate settings on this product; returns (tile_cfg, combine)."""
+    call = MulCall(layout, f, g, workspace, stream)
+    call.ws = (workspace or Workspace()).get(2 * call.ws_bytes)   # room for the combine setting
+    t, c = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    _check(lib().pm_autotune(ctypes.byref(call.L), ctypes.byref(call.cf), ctypes.byref(call.cg),
+                             ctypes.byref(call.h), ctypes.c_void_p(call.ws.data_ptr()), call.ws.numel(), call.sp,
+                             ctypes.byref(t), ctypes.byref(c)), "pm_autotune")
+    return int(t.value), int(c.value)
+
+
+def autotune_reset():
+    lib().pm_autotune_reset()
+
+
+class Server:
+    """Continuous-batching server (pm_server_*): one HBM arena and a scheduler thread."""
+
+    def __init__(self, hbm_budget_bytes: int, nstreams: int = 4):
+        self.h = lib().pm_server_create(int(hbm_budget_bytes), int(nstreams))
+        if not self.h:
+            raise RuntimeError("pm_server_create failed: " + lib().pm_last_error().decode())
+        self.keep = {}
+
+    def submit(self, layout, f: DevPoly, g: DevPoly, out) -> int:
+        """Queue h = f * g into out = (keys, coefs, n) tensors; returns a ticket."""
+        L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+        hk, hc, hn = out
+        h = pm_poly(min(hk.numel(), hc.numel()), hn.data_ptr(), hk.data_ptr(), hc.data_ptr())
+        t = ctypes.c_uint64(0)
+        _check(lib().pm_server_submit(self.h, ctypes.byref(L), ctypes.byref(_cpoly(f)), ctypes.byref(_cpoly(g)),
+                                      ctypes.byref(h), ctypes.byref(t)), "pm_server_submit")
+        self.keep[int(t.value)] = (f, g, out)
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        d, s = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().pm_server_poll(self.h, ticket, ctypes.byref(d), ctypes.byref(s)), "pm_server_poll")
+        return bool(d.value), int(s.value)
+
+    def wait(self, ticket: int) -> int:
+        s = ctypes.c_int32(0)
+        _check(lib().pm_server_wait(self.h, ticket, ctypes.byref(s)), "pm_server_wait")
+        return int(s.value)
+
+    def latencies_us(self):
+        n = lib().pm_server_latencies(self.h, None, 0)
+        buf = (ctypes.c_double * max(n, 1))()
+        n = lib().pm_server_latencies(self.h, buf, n)
+        return [float(buf[i]) for i in range(n)]
+
+    def close(self):
+        if self.h:
+            lib().pm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

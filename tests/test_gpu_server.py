@@ -1,0 +1,103 @@
+"""Serving loop: continuous batching with HBM-budget admission.  Each result
+is the same alone and in the mix (FP64 bit for bit), and matches the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle
+from paper_1303_7425_amd import workloads as W
+
+
+def _pm():
+    from paper_1303_7425_amd import polymul
+    return polymul
+
+
+def test_server_mix_matches_alone_and_oracle():
+    import torch
+    pm = _pm()
+    reqs = W.config5_stream(40, rate_per_s=2000.0, seed=5, large_frac=0.1, large_n=12, small_range=(3, 7))
+    print(f"[server] {len(reqs)} requests", flush=True)
+    srv = pm.Server(2 << 30, nstreams=4)
+    tickets, outs, devs = [], [], []
+    t0 = time.perf_counter()
+    for r in reqs:
+        while time.perf_counter() - t0 < r.arrival_s:
+            pass
+        f, g = pm.to_device(r.f), pm.to_device(r.g)
+        cap, _ = pm.bound((r.f.layout.nvars, r.f.layout.bits, "modp"), f, g)
+        out = pm.alloc_out(cap, "modp")
+        tickets.append(srv.submit((r.f.layout.nvars, r.f.layout.bits, "modp"), f, g, out))
+        outs.append(out)
+        devs.append((f, g))
+    for t in tickets:
+        assert srv.wait(t) == pm.PM_OK
+    torch.cuda.synchronize()
+    lat = srv.latencies_us()
+    assert len(lat) == len(reqs)
+    for i, r in enumerate(reqs):
+        k, c, n = outs[i]
+        nn = int(n.item())
+        gk = k[:nn].cpu().numpy().view(np.uint64)
+        gc = c[:nn].cpu().numpy().view(np.uint64)
+        ak, ac = pm.mul((r.f.layout.nvars, r.f.layout.bits, "modp"), *devs[i]).numpy()
+        assert np.array_equal(gk, ak) and np.array_equal(gc, ac), i
+        if i % 4 == 0:
+            wk, wc, _ = oracle.mul(r.f, r.g)
+            assert np.array_equal(gk, wk) and np.array_equal(gc, wc), i
+    srv.close()
+
+
+def test_server_f64_identical_to_alone():
+    import torch
+    pm = _pm()
+    srv = pm.Server(1 << 30, nstreams=3)
+    rng = W.rng_for(12)
+    items = []
+    for k in range(10):
+        f = W.with_random_coefs(W.sparse_power(3 + k % 4, "f", 12, "modp"), rng, "f64")
+        g = W.with_random_coefs(W.sparse_power(3 + (k * 3) % 5, "g", 12, "modp"), rng, "f64")
+        fd, gd = pm.to_device(f), pm.to_device(g)
+        cap, _ = pm.bound((5, 12, "f64"), fd, gd)
+        out = pm.alloc_out(cap, "f64")
+        items.append((f, g, fd, gd, out, srv.submit((5, 12, "f64"), fd, gd, out)))
+    for f, g, fd, gd, out, t in items:
+        assert srv.wait(t) == pm.PM_OK
+    torch.cuda.synchronize()
+    for f, g, fd, gd, out, t in items:
+        n = int(out[2].item())
+        ak, ac = pm.mul((5, 12, "f64"), fd, gd).numpy()
+        assert np.array_equal(out[0][:n].cpu().numpy().view(np.uint64), ak)
+        assert np.array_equal(out[1][:n].cpu().numpy().view(np.uint64), ac.view(np.uint64))
+    srv.close()
+
+
+def test_server_errors_and_budget():
+    pm = _pm()
+    srv = pm.Server(64 << 20, nstreams=2)
+    f, g = W.config3("modp", n=6)
+    fd, gd = pm.to_device(f), pm.to_device(g)
+    small = pm.alloc_out(4, "modp")
+    t = srv.submit((5, 12, "modp"), fd, gd, small)
+    assert srv.wait(t) == pm.PM_ECAPACITY
+    bad = W.Poly(f.layout, f.keys[::-1].copy(), f.coefs)
+    cap, _ = pm.bound((5, 12, "modp"), fd, gd)
+    t = srv.submit((5, 12, "modp"), pm.to_device(bad), gd, pm.alloc_out(cap, "modp"))
+    assert srv.wait(t) == pm.PM_EUNSORTED
+    # needs more workspace than the whole arena
+    fb, gb = W.config3("modp", n=12)
+    fbd, gbd = pm.to_device(fb), pm.to_device(gb)
+    capb, _ = pm.bound((5, 12, "modp"), fbd, gbd)
+    t = srv.submit((5, 12, "modp"), fbd, gbd, pm.alloc_out(capb, "modp"))
+    assert srv.wait(t) == pm.PM_ENOMEM
+    # a valid one still goes through afterwards
+    out = pm.alloc_out(cap, "modp")
+    t = srv.submit((5, 12, "modp"), fd, gd, out)
+    assert srv.wait(t) == pm.PM_OK
+    want = oracle.mul(f, g)
+    n = int(out[2].item())
+    assert np.array_equal(out[0][:n].cpu().numpy().view(np.uint64), want[0])
+    srv.close()
