@@ -19,6 +19,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sparse5_n12_modp_hbm_traffic.json")
+
+
+def measured_traffic(label):
+    """Scaled rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch of `label`,
+    or None when the kernels changed since the counters were taken."""
+    import hashlib
+    try:
+        prof = json.load(open(TRAFFIC_PROFILE))
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_1303_7425_amd", "csrc", "pm_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != prof.get("kernel_source_sha256_16"):
+        return None
+    e = prof["per_launch"].get(label)
+    return None if e is None else e["fetch_bytes"] + e["write_bytes"]
 
 
 def parse():
@@ -33,6 +50,8 @@ def parse():
                     help="sparse: the large sparse product (default JSON line); batch: the 4096-product "
                          "batched workload, batched graph launches vs per-product calls; serve: Poisson "
                          "arrivals through the continuous-batching server")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy 512 MiB three times (counter scaling for HBM traffic)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--wave-gib", type=float, default=96.0, help="HBM per memory wave (outputs + workspace)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -234,6 +253,13 @@ def main():
     sweep_bytes = staged * (kbytes + vbytes) * 2  # read key+payload, write key+payload
     achieved = sweep_bytes / (sweep_avg_ms * 1e-3) / 1e9 if sweep_avg_ms > 0 else 0.0
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -267,7 +293,8 @@ def main():
             "bits_per_var": 12,
         },
         "roofline": {"bound": "hbm", "kernel": "onesweep (one LSD radix pass)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("onesweep pass (reads staged items)") if args.ring == "modp" else None,
                      "algorithmic_bytes_per_launch": sweep_bytes, "avg_launch_ms": sweep_avg_ms,
                      "sorted_items": staged, "passes": passes, "key_bytes": kbytes,
                      "payload_bytes": vbytes},
