@@ -184,10 +184,12 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
  * Process-wide tuning of later calls (the autotuner's knobs):
  *   tile_cfg     -1 automatic, else 0: 32x64, 1: 64x64, 2: 128x128 term tiles
  *                (LDS tile combine and dense path)
- *   combine      -1 automatic; 0: the sparse path radix-sorts term-pair indices
- *                and regenerates each product in the reduction; 1: exact rings
- *                first combine f-block x g-block tiles in LDS and sort the
- *                combined (monomial, coefficient) pairs
+ *   combine      sparse path: -1 automatic; 0: radix-sort term-pair indices and
+ *                regenerate each product in the reduction; 1: exact rings first
+ *                combine f-block x g-block tiles in LDS and sort the combined
+ *                (monomial, coefficient) pairs; 2: output-key intervals (grid
+ *                sample of the pp-matrix, per-interval merge in LDS, no global
+ *                sort; products whose degree box has fewer than 2^32 cells)
  *   allow_dense  0: never use the degree-box path
  * Results do not depend on these settings (FP64 always sorts pair indices).
  */
@@ -223,8 +225,9 @@ int pm_profile_enable(int32_t enable);
 int pm_profile_read(int32_t i, char *name, int32_t name_cap, double *total_ms, int64_t *launches);
 
 /*
- * Autotuner.  Runs h = f * g once per candidate setting (LDS tile combine on
- * or off for exact rings; tile shape for the degree-box path), times each with
+ * Autotuner.  Runs h = f * g once per candidate setting (sparse path: key
+ * intervals, pair-index sort, LDS tile combine; tile shape for the degree-box
+ * path), times each with
  * HIP events on `stream`, and remembers the fastest for the product's size
  * class (ring, path, floor(log2(term pairs))).  Later calls with automatic
  * settings (pm_set_tuning(-1, -1, ...), the default) use the remembered choice

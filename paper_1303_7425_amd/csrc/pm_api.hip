@@ -162,7 +162,7 @@ int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cp
     }
     (void)fb;
     return plan_build(nv, (int)L->bits, L->ring, in, (const uint64_t *)hstats,
-                      (const uint32_t *)(hstats + ((sb + 255) & ~(size_t)255)), tune, P);
+                      (const uint32_t *)(hstats + ((sb + 255) & ~(size_t)255)), tune, P, device_cus());
 }
 
 // Upload the descriptor block of plan P (output pointers filled) and enqueue
@@ -179,6 +179,8 @@ int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st) {
     memcpy(pin + (P.o_dpart_pre - d0), P.dpart_pre.data(), 8 * P.dpart_pre.size());
     if (!P.dseg.empty()) memcpy(pin + (P.o_dseg - d0), P.dseg.data(), 4 * P.dseg.size());
     memcpy(pin + (P.o_cpre - d0), P.cpre.data(), 8 * P.cpre.size());
+    memcpy(pin + (P.o_iv_pre - d0), P.iv_pre.data(), 8 * P.iv_pre.size());
+    if (!P.iv_seg.empty()) memcpy(pin + (P.o_iv_seg - d0), P.iv_seg.data(), 4 * P.iv_seg.size());
     hipError_t e = hipMemcpyAsync((char *)ws + d0, pin, P.r_desc.bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(hs.ev, st);
     if (e != hipSuccess) {
@@ -403,9 +405,11 @@ int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, c
     if (dense) {
         for (int t = 0; t < N_TILE_CFGS; t++) cands.push_back({t, 0});
     } else if (layout->ring != PM_F64) {
+        cands.push_back({-1, 2});
         cands.push_back({-1, 0});
         cands.push_back({0, 1});
     } else {
+        cands.push_back({-1, 2});
         cands.push_back({-1, 0});
     }
     hipEvent_t e0, e1;
@@ -472,7 +476,7 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
 
 int pm_set_tuning(int32_t tile_cfg, int32_t combine, int32_t allow_dense) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (tile_cfg < -1 || tile_cfg >= N_TILE_CFGS || combine < -1 || combine > 1) return PM_EINVAL;
+    if (tile_cfg < -1 || tile_cfg >= N_TILE_CFGS || combine < -1 || combine > 2) return PM_EINVAL;
     g_tune.tile_cfg = tile_cfg;
     g_tune.combine = combine;
     g_tune.allow_dense = allow_dense ? 1 : 0;

@@ -22,7 +22,10 @@ enum SegMode : int {
     SEG_COMBINE = 1,  // tiles combined in LDS, then global radix sort + segmented reduction
     SEG_RAW = 2,      // pair indices sorted by key (products regenerated), then reduction
     SEG_DENSE = 3,    // accumulated directly into the degree box, then compaction
+    SEG_IVAL = 4,     // output-key intervals owned by workgroups, merged in LDS (no global sort)
 };
+
+constexpr int IV_SAMPLES_MAX = 4096;   // grid samples per product ((l+1)^2, l <= 63)
 
 constexpr int NTHREADS = 256;          // threads per workgroup (4 wave64s)
 constexpr int IPT = 16;                // items per thread in sort / reduce partitions
@@ -71,6 +74,8 @@ struct DevSeg {
     Div32 nb_div;                  // division by nb: pair index -> (row, column) (SEG_RAW)
     i64 dpart_first;               // first compaction partition (SEG_DENSE)
     i64 var_off;                   // offset of this product's VarParam entries
+    i64 iv_l;                      // grid parameter l (SEG_IVAL): (l+1)^2 samples
+    i64 iv_samp_off, iv_spl_off;   // offsets of its samples and splitters
     u64 lo_key;                    // packed key of the smallest output exponent vector
     u64 *hk, *hc;                  // result arrays
     i64 *n_out;
@@ -122,6 +127,15 @@ struct Ctx {
     u64 *look_cmp;              // dense compaction lookback [ndparts]
     u64 *look_tile;             // staging offsets of combined tiles [ntiles]
     u32 *counters;              // work-queue tickets and error flags
+    void *iv_samp, *iv_spl;     // grid samples / interval bounds (SEG_IVAL)
+    u32 *iv_cur;                // per-workgroup row cursors
+    i64 iv_maxrows;
+    struct IvalItem *iv_items_arr;
+    u64 *iv_off;                // result offset of every interval
+    const i64 *iv_pre;          // [nivseg+1] interval-item prefix over SEG_IVAL products
+    const i32 *iv_seg;
+    i32 nivseg;
+    i64 iv_items;
     i32 nseg, ntseg, ndseg;
     i32 nvars, bits, passes, ring;
     i64 ntiles, ndparts;
@@ -136,6 +150,7 @@ enum Counter : int {
     CNT_SORT = 2,                   // + pass (MAX_PASSES slots)
     CNT_REDUCE = CNT_SORT + MAX_PASSES,
     CNT_COMPACT,
+    CNT_IVAL,
     CNT_ERR_SPIN,                   // a lookback wait hit its iteration bound
     CNT_COUNT
 };

@@ -737,6 +737,8 @@ __global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
 
 }  // namespace pm
 
+#include "pm_ival.hpp"
+
 // ===========================================================================
 // Host-side launch sequence
 // ===========================================================================
@@ -919,6 +921,22 @@ static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
     if (P.ntiles > 0) {
         if constexpr (RING != RING_F64) launch_tile<K, RING>(P, C, st, grid_for(P.ntiles, cus * 8));
     }
+    if (P.nival > 0) {
+        if constexpr (sizeof(K) == 4) {
+            {
+                ProfScope ps("ival_split", st);
+                hipLaunchKernelGGL((k_ival_sample<K>), dim3(16, P.nseg), dim3(NTHREADS), 0, st, C);
+                hipLaunchKernelGGL((k_ival_split<K>), dim3(P.nseg), dim3(NTHREADS), 0, st, C);
+            }
+            {
+                ProfScope ps("ival", st);
+                hipLaunchKernelGGL((k_ival<K, RING>), dim3(P.iv_grid), dim3(NTHREADS), 0, st, C);
+            }
+            ProfScope ps("ival_concat", st);
+            hipLaunchKernelGGL(k_ival_scan, dim3(P.nival), dim3(NTHREADS), 0, st, C);
+            hipLaunchKernelGGL((k_ival_copy<K>), dim3(grid_for(P.iv_items, cus * 8)), dim3(NTHREADS), 0, st, C);
+        }
+    }
     if (P.nsparse > 0) {
         if (P.raw) {
             launch_sort_reduce<K, u32, RING>(P, C, st, cus);
@@ -994,6 +1012,16 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.ring = P.ring;
     C.ntiles = P.ntiles;
     C.raw = P.raw;
+    C.iv_samp = b + P.o_iv_samp;
+    C.iv_spl = b + P.o_iv_spl;
+    C.iv_cur = (u32 *)(b + P.o_iv_cur);
+    C.iv_maxrows = P.iv_maxrows;
+    C.iv_items_arr = (IvalItem *)(b + P.o_iv_items);
+    C.iv_off = (u64 *)(b + P.o_iv_off);
+    C.iv_pre = (const i64 *)(b + P.o_iv_pre);
+    C.iv_seg = (const i32 *)(b + P.o_iv_seg);
+    C.nivseg = (i32)P.iv_seg.size();
+    C.iv_items = P.iv_items;
     const int cus = device_cus_cached();
     // A ticket may cover several consecutive work items only where no
     // look-back follows: a batch's first item would otherwise wait for the

@@ -2,6 +2,7 @@
 #include "pm_plan.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 
@@ -56,7 +57,7 @@ static int bitlen128(unsigned __int128 x) {
 }
 
 int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, const uint64_t *stats,
-               const uint32_t *flags, const Tuning &tune_in, Plan &P) {
+               const uint32_t *flags, const Tuning &tune_in, Plan &P, int cus) {
     const int S = (int)in.size();
     P = Plan();
     P.nseg = S;
@@ -173,6 +174,19 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         if ((unsigned __int128)P.segs[q].na * P.segs[q].nb > 0xFFFFFFFFull) idx_fits = false;
         if (box[q] >= ((unsigned __int128)1 << 64)) sentinel_ok = false;
     }
+    // output-key intervals: 32-bit compressed keys and 32-bit pair indices
+    if (P.ksize == 4 && idx_fits && tune.combine == 2) {
+        for (int q = 0; q < S; q++) {
+            if (P.segs[q].mode != SEG_RAW) continue;
+            DevSeg &d = P.segs[q];
+            d.mode = SEG_IVAL;
+            const double target = std::max(1.0, (double)d.na * (double)d.nb / 32768.0);
+            int64_t l = (int64_t)std::ceil(std::sqrt(target)) - 1;
+            l = std::max<int64_t>(0, std::min<int64_t>(l, 63));
+            l = std::min<int64_t>(l, std::min(d.na, d.nb));
+            d.iv_l = l;
+        }
+    }
     bool combine = ring != RING_F64 && sentinel_ok && (tune.combine == 1 || !idx_fits);
     if (!combine && !idx_fits) return PM_ENOMEM;  // FP64 product of more than 2^32 - 1 term pairs
     P.raw = combine ? 0 : 1;
@@ -181,6 +195,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         if (P.segs[q].mode == SEG_RAW && combine) P.segs[q].mode = SEG_COMBINE;
     bool any_sparse = false;
     for (int q = 0; q < S; q++) any_sparse |= P.segs[q].mode == SEG_RAW || P.segs[q].mode == SEG_COMBINE;
+    if (!any_sparse) P.passes = 0;
     if (P.raw && any_sparse && P.passes == 0) P.passes = 1;  // pass 0 also generates the items
 
     // tile shape: explicit, or the largest one that still gives >= 512 tiles
@@ -229,6 +244,21 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             P.tile_pre.push_back(P.tile_pre.back() + tmn * tnn);
         }
         if (d.mode == SEG_RAW) d.nb_div = make_div32((uint32_t)d.nb);
+        if (d.mode == SEG_IVAL) {
+            d.nb_div = make_div32((uint32_t)d.nb);
+            d.stage_base = nstage;
+            d.stage_bound = d.na * d.nb;
+            nstage += d.stage_bound;
+            d.iv_samp_off = P.iv_nsamp;
+            P.iv_nsamp += (d.iv_l + 1) * (d.iv_l + 1);
+            d.iv_spl_off = P.iv_nspl;
+            P.iv_nspl += (d.iv_l + 1) * (d.iv_l + 1) + 2;
+            if (P.iv_pre.empty()) P.iv_pre.push_back(0);
+            P.iv_seg.push_back(q);
+            P.iv_pre.push_back(P.iv_pre.back() + (d.iv_l + 1) * (d.iv_l + 1) + 1);
+            P.iv_maxrows = std::max<int64_t>(P.iv_maxrows, d.na);
+            P.nival++;
+        }
         if (d.mode == SEG_COMBINE || d.mode == SEG_RAW) {
             d.stage_base = nstage;
             d.stage_bound = d.na * d.nb;
@@ -249,6 +279,9 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.ntiles = P.tile_pre.back();
     P.ndparts = P.dpart_pre.back();
     P.nstage = nstage;
+    if (P.iv_pre.empty()) P.iv_pre.push_back(0);
+    P.iv_items = P.iv_pre.back();
+    P.iv_grid = (int)std::max<int64_t>(1, std::min<int64_t>(P.iv_items, (int64_t)cus * 2));
     P.nbox = nbox;
     P.nck = nck;
 
@@ -271,6 +304,8 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_dpart_pre = take(8 * P.dpart_pre.size());
     P.o_dseg = take(4 * std::max<size_t>(1, P.dseg.size()));
     P.o_cpre = take(8 * P.cpre.size());
+    P.o_iv_pre = take(8 * P.iv_pre.size());
+    P.o_iv_seg = take(4 * std::max<size_t>(1, P.iv_seg.size()));
     P.r_desc.off = desc0;
     P.r_desc.bytes = off - desc0;
     const size_t zero0 = off;
@@ -285,11 +320,17 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.r_zero.off = zero0;
     P.r_zero.bytes = off - zero0;
     P.o_ppre = take((size_t)8 * (S + 1));
+    P.o_iv_samp = take((size_t)P.ksize * std::max<int64_t>(1, P.iv_nsamp));
+    P.o_iv_spl = take((size_t)P.ksize * std::max<int64_t>(1, P.iv_nspl));
+    P.o_iv_cur = take((size_t)4 * std::max<int64_t>(1, (int64_t)P.iv_grid * P.iv_maxrows));
+    P.o_iv_items = take((size_t)16 * std::max<int64_t>(1, P.iv_items));
+    P.o_iv_off = take((size_t)8 * std::max<int64_t>(1, P.iv_items));
     P.o_ck = take((size_t)P.ksize * std::max<int64_t>(1, nck));
-    P.o_stAk = take((size_t)P.ksize * std::max<int64_t>(1, nstage));
-    P.o_stAv = take((size_t)P.vsize * std::max<int64_t>(1, nstage));
+    const int64_t nstageA = P.nival ? 1 : nstage;
+    P.o_stAk = take((size_t)P.ksize * std::max<int64_t>(1, nstageA));
+    P.o_stAv = take((size_t)P.vsize * std::max<int64_t>(1, nstageA));
     P.o_stBk = take((size_t)P.ksize * std::max<int64_t>(1, nstage));
-    P.o_stBv = take((size_t)P.vsize * std::max<int64_t>(1, nstage));
+    P.o_stBv = take((size_t)(P.nival ? 8 : P.vsize) * std::max<int64_t>(1, nstage));
     P.total = off;
     return PM_OK;
 }

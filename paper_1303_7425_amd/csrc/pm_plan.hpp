@@ -26,7 +26,7 @@ constexpr int N_TILE_CFGS = 3;
 
 struct Tuning {
     int tile_cfg = -1;       // -1: choose automatically
-    int combine = -1;        // exact rings: 1 LDS tile combine before the sort, 0 pair-index sort, -1 auto
+    int combine = -1;        // sparse path: -1 auto, 0 pair-index sort, 1 LDS tile combine + sort, 2 key intervals
     int allow_dense = 1;     // permit the degree-box path
     double dense_ratio = 2;  // dense when box * dense_ratio <= na * nb
     int64_t dense_max_cells = int64_t(1) << 27;
@@ -62,6 +62,11 @@ struct Plan {
     std::vector<int32_t> tile_seg, dseg;
     int64_t ntiles = 0, ndparts = 0, nparts_bound = 0;
     int raw = 1;        // sparse products sort (key, pair index); else (key, coefficient)
+    int nival = 0;      // products on the output-key interval path
+    std::vector<int64_t> iv_pre;
+    std::vector<int32_t> iv_seg;
+    int64_t iv_items = 0, iv_maxrows = 0, iv_nsamp = 0, iv_nspl = 0;
+    int iv_grid = 1;
     int vsize = 4;      // payload bytes of a sort item
     int64_t nstage = 0, nbox = 0, nck = 0;
     int nsparse = 0, ndense = 0;
@@ -69,6 +74,7 @@ struct Plan {
     Region r_stats, r_flags, r_desc, r_zero;
     size_t o_segs = 0, o_vars = 0, o_tile_pre = 0, o_tile_seg = 0, o_dpart_pre = 0, o_dseg = 0, o_cpre = 0;
     size_t o_dyn = 0, o_counters = 0, o_hist = 0, o_look = 0, o_look_red = 0, o_look_cmp = 0, o_look_tile = 0, o_box = 0;
+    size_t o_iv_samp = 0, o_iv_spl = 0, o_iv_cur = 0, o_iv_items = 0, o_iv_off = 0, o_iv_pre = 0, o_iv_seg = 0;
     size_t o_ppre = 0, o_ck = 0, o_stAk = 0, o_stAv = 0, o_stBk = 0, o_stBv = 0;
     size_t total = 0;
 };
@@ -84,7 +90,7 @@ struct SegInput {
 // Returns PM_OK or an error code.  `stats` holds [nseg][2 sides][min|max][nvars]
 // and `flags` [nseg][2].  Output pointers of the segments are filled later.
 int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, const uint64_t *stats,
-               const uint32_t *flags, const Tuning &tune, Plan &plan);
+               const uint32_t *flags, const Tuning &tune, Plan &plan, int cus = 256);
 
 // Byte size of the region holding the statistics, for a call with nseg products.
 size_t stats_region_bytes(int nseg, int nvars);

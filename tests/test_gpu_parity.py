@@ -104,7 +104,8 @@ def test_random_6var_ragged(ring, na, nb):
     check(f, g, f"rand {na}x{nb}")
 
 
-@pytest.mark.parametrize("mode", ["auto", "pairs", "combine", "nodense", "nodense_combine", "tile1", "tile2"])
+@pytest.mark.parametrize("mode", ["auto", "pairs", "combine", "intervals", "nodense", "nodense_combine",
+                                  "nodense_intervals", "tile1", "tile2"])
 def test_tuning_modes_same_result(mode):
     pm = _pm()
     if mode == "pairs":
@@ -115,6 +116,10 @@ def test_tuning_modes_same_result(mode):
         pm.set_tuning(-1, 0, False)
     elif mode == "nodense_combine":
         pm.set_tuning(-1, 1, False)
+    elif mode == "intervals":
+        pm.set_tuning(-1, 2, True)
+    elif mode == "nodense_intervals":
+        pm.set_tuning(-1, 2, False)
     elif mode == "tile1":
         pm.set_tuning(1, -1, True)
     elif mode == "tile2":
@@ -263,6 +268,26 @@ def test_config2_full_closed_form_and_evaluation():
 def test_config3_full(ring):
     f, g = W.config3(ring)
     check(f, g, f"cfg3 {ring}")
+
+
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_config3_full_pair_sort_path(ring):
+    pm = _pm()
+    pm.set_tuning(-1, 0, True)
+    f, g = W.config3(ring)
+    check(f, g, f"cfg3 pair sort {ring}")
+
+
+def test_dense_family_through_intervals():
+    # high multiplicity (up to thousands of pairs per monomial) on the interval
+    # path: exercises bucket refinement and the single-monomial accumulation
+    pm = _pm()
+    pm.set_tuning(-1, 2, False)
+    for ring in ("modp", "i64"):
+        f = W.dense_power(14, 4, 16, ring)
+        check(f, W.add_constant(f, 1), f"dense n=14 intervals {ring}")
+    f = W.dense_power(14, 4, 16, "f64")
+    check(f, W.add_constant(f, 1), "dense n=14 intervals f64")
 
 
 def test_config3_modp_lds_combine():
