@@ -83,10 +83,13 @@ typedef struct {
 } pm_cpoly;
 
 /* Result: device arrays of `capacity` terms; *n_out receives the term count.
- * If the product has more than `capacity` terms, the first `capacity` terms
- * are written and *n_out still receives the full count (so *n_out > capacity
- * signals truncation).  A capacity of at least the bound from pm_mul_bound
- * never truncates. */
+ * *n_out > capacity signals truncation, and a capacity of at least *n_out
+ * avoids it: *n_out is then the full term count or, on the sorted path when
+ * terms cancel, the number of distinct monomials before the cancelled ones
+ * are dropped (result slots are assigned before the sums are known).  A
+ * truncated result holds the first terms of the product, followed by entries
+ * with zero coefficients.  A capacity of at least the bound from
+ * pm_mul_bound never truncates. */
 typedef struct {
     int64_t capacity;
     int64_t *n_out;

@@ -90,6 +90,8 @@ struct DevSegDyn {
     i64 n;                         // pairs to sort
     i64 part_first;                // first sort / reduce partition
     i64 nparts;
+    i64 heads;                     // distinct keys after the sort (result slots incl. cancelled ones)
+    unsigned long long zeros;      // slots whose sum cancelled to zero
 };
 
 // Per product and variable: field position and the mixed-radix compression.
@@ -152,6 +154,8 @@ enum Counter : int {
     CNT_COMPACT,
     CNT_IVAL,
     CNT_ERR_SPIN,                   // a lookback wait hit its iteration bound
+    CNT_ZEROS,                      // some product of the launch has cancelled terms
+    CNT_ZCOMPACT,
     CNT_COUNT
 };
 
@@ -327,14 +331,19 @@ __device__ inline u64 wave_sum_u64(u64 v) {
     return v;
 }
 
+// Publishes partition p's own aggregate: its inclusive prefix when p is the
+// product's first partition.  Publishing early, and resolving the prefix
+// later, gives the predecessors time to publish theirs.
+__device__ inline void lb_publish(u64 *slot, i64 first, i64 p, u32 tag, u64 value) {
+    lb_store(slot, lb_pack(tag, p == first ? LB_INC : LB_AGG, value));
+}
+
 // Per-thread decoupled look-back over a strided counter array (one counter
-// per digit), reading up to four predecessors per round trip.
-__device__ inline u64 lookback_batched(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
-    if (p == first) {
-        lb_store(look + p * stride, lb_pack(tag, LB_INC, value));
-        return 0;
-    }
-    lb_store(look + p * stride, lb_pack(tag, LB_AGG, value));
+// per digit), reading up to four predecessors per round trip.  The partition
+// has already published its aggregate with lb_publish.
+__device__ inline u64 lookback_batched_resolve(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value,
+                                               u32 *err) {
+    if (p == first) return 0;
     u64 prefix = 0;
     i64 j = p - 1;
     u32 spins = 0;
@@ -368,17 +377,19 @@ __device__ inline u64 lookback_batched(u64 *look, i64 stride, i64 first, i64 p, 
     return prefix;
 }
 
+__device__ inline u64 lookback_batched(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
+    lb_publish(look + p * stride, first, p, tag, value);
+    return lookback_batched_resolve(look, stride, first, p, tag, value, err);
+}
+
 // Wave-cooperative decoupled look-back for one counter per partition.  All
 // 64 lanes of one wave call it with the same (first, p); lane l inspects
 // predecessor p-1-l, so one round trip covers 64 predecessors.  Returns the
-// exclusive prefix of `value` over partitions [first, p) in every lane.
-__device__ inline u64 lookback_wave(u64 *look, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
+// exclusive prefix of `value` over partitions [first, p) in every lane.  The
+// partition has already published its aggregate with lb_publish.
+__device__ inline u64 lookback_wave_resolve(u64 *look, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
     const u32 lane = lane_id();
-    if (p == first) {
-        if (lane == 0) lb_store(look + p, lb_pack(tag, LB_INC, value));
-        return 0;
-    }
-    if (lane == 0) lb_store(look + p, lb_pack(tag, LB_AGG, value));
+    if (p == first) return 0;
     u64 prefix = 0;
     i64 top = p - 1;
     while (true) {
@@ -410,6 +421,11 @@ __device__ inline u64 lookback_wave(u64 *look, i64 first, i64 p, u32 tag, u64 va
     }
     if (lane == 0) lb_store(look + p, lb_pack(tag, LB_INC, prefix + value));
     return prefix;
+}
+
+__device__ inline u64 lookback_wave(u64 *look, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
+    if (lane_id() == 0) lb_publish(look + p, first, p, tag, value);
+    return lookback_wave_resolve(look, first, p, tag, value, err);
 }
 
 // Largest index s in [0, n) with pre[s] <= x (pre ascending, pre[0] = 0).

@@ -384,156 +384,185 @@ __device__ inline void seg_digit_bases(Ctx &C, int pass, int q, u64 *s_base, u64
 // product.  Ranks come from per-wave ballot "match" masks (peers with the same
 // digit) and per-wave digit counters in LDS; a digit's product-wide position
 // is its digit offset plus a decoupled look-back over the product's earlier
-// partitions.  GEN: pass 0 of SEG_RAW, where items are generated from the
-// pair index instead of read.  The histogram of the next digit is counted on
-// the way (input and output are the same multiset).
+// partitions.  The partition publishes its digit counts as soon as they are
+// known and resolves its prefix only after the LDS-local reorder, so that
+// the predecessors have published by then.  GEN: pass 0 of SEG_RAW, where
+// items are generated from the pair index instead of read.  The histogram of
+// the next digit is counted on the way (input and output are the same
+// multiset).  FULL partitions (PART items) take a body without item guards.
 // ---------------------------------------------------------------------------
+template <typename K, typename V>
+struct OsSmem {
+    static constexpr int NW = NTHREADS / 64;
+    union {
+        K k[PART];
+        V v[PART];
+    } buf;
+    unsigned char dig[PART];
+    u32 wh[NW][RADIX];
+    u32 loff[RADIX];
+    i64 goff[RADIX];
+    u64 base[RADIX];
+    u32 nh[RADIX];
+    u32 scan[NW];
+    u64 scan64[NW];
+    i64 p, pn;
+};
+
+template <typename K, typename V, bool GEN, bool FULL>
+__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const DevSeg &s, int pass, i64 p, i64 first,
+                                             i64 c, i64 n_q, int n, const K *__restrict__ kin,
+                                             const V *__restrict__ vin, K *__restrict__ kout, V *__restrict__ vout,
+                                             bool next_hist, u32 *ticket) {
+    constexpr int NW = OsSmem<K, V>::NW;
+    const int shift = pass * RADIX_BITS;
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    const u32 tag = (u32)pass + 1;
+    const i64 start = s.stage_base + c * PART;
+    const K *ckeys = (const K *)C.ck;
+
+    // load, warp-striped: item k of lane l in wave w is w*64*IPT + k*64 + l
+    K key[IPT];
+    V val[IPT];
+    u32 rk[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+        if constexpr (GEN) {
+            const u32 x = (u32)(c * PART + idx);
+            key[k] = (FULL || idx < n) ? raw_key<K>(s, ckeys, x) : (K)0;
+            val[k] = (V)x;
+        } else {
+            key[k] = (FULL || idx < n) ? kin[start + idx] : (K)0;
+        }
+    }
+    if constexpr (!GEN) {
+        // payloads are only permuted: issue their loads now so they overlap the ranking
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+            val[k] = (FULL || idx < n) ? vin[start + idx] : (V)0;
+        }
+    }
+    // per-wave stable ranking
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+        const bool valid = FULL || idx < n;
+        const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
+        u64 peers = FULL ? ~0ull : __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; b++) {
+            const u64 m = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        const u32 before = mbcnt(peers);
+        const u32 cnt = (u32)__popcll(peers);
+        const u32 old = valid ? S.wh[w][d] : 0;
+        if (valid && before == 0) S.wh[w][d] = old + cnt;
+        rk[k] = old + before;
+        if (next_hist && valid) atomicAdd(&S.nh[(u32)((key[k] >> (shift + RADIX_BITS)) & (RADIX - 1))], 1u);
+    }
+    __syncthreads();
+    // digit totals, wave prefixes, local digit offsets; publish the totals
+    const int d = threadIdx.x;  // RADIX == NTHREADS
+    u32 tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ww++) {
+        const u32 x = S.wh[ww][d];
+        S.wh[ww][d] = tot;
+        tot += x;
+    }
+    lb_publish(C.look + p * RADIX + d, first, p, tag, tot);
+    u32 all;
+    const u32 loff = block_excl_scan<u32>(tot, S.scan, all);
+    S.loff[d] = loff;
+    __syncthreads();
+    // keys into LDS in sorted order
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+        if (FULL || idx < n) {
+            const u32 dk = (u32)((key[k] >> shift) & (RADIX - 1));
+            const u32 pos = S.loff[dk] + S.wh[w][dk] + rk[k];
+            rk[k] = pos;
+            S.buf.k[pos] = key[k];
+            S.dig[pos] = (unsigned char)dk;
+        }
+    }
+    // product-wide offset of this digit in this partition
+    const u64 prefix = lookback_batched_resolve(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
+    S.goff[d] = (i64)(S.base[d] + prefix) - (i64)loff;
+    u32 tk = 0;
+    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition, claimed while this one scatters
+    __syncthreads();
+    const i64 lo = s.stage_base, span = n_q;
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+        const int i = (int)threadIdx.x + k * NTHREADS;
+        if (FULL || i < n) {
+            const i64 o = S.goff[S.dig[i]] + i;
+            if ((u64)(o - lo) < (u64)span) kout[o] = S.buf.k[i];
+            else atomicOr(&C.counters[CNT_ERR_SPIN], 2u);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+        if (FULL || idx < n) S.buf.v[rk[k]] = val[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+        const int i = (int)threadIdx.x + k * NTHREADS;
+        if (FULL || i < n) {
+            const i64 o = S.goff[S.dig[i]] + i;
+            if ((u64)(o - lo) < (u64)span) vout[o] = S.buf.v[i];
+        }
+    }
+    if (threadIdx.x == 0) S.pn = (i64)tk;
+    __syncthreads();
+}
+
 template <typename K, typename V, bool GEN>
 __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
-    constexpr int NW = NTHREADS / 64;
-    __shared__ union {
-        K k[PART];
-        V v[PART];
-    } s_buf;
-    __shared__ unsigned char s_dig[PART];
-    __shared__ u32 s_wh[NW][RADIX];
-    __shared__ u32 s_loff[RADIX];
-    __shared__ i64 s_goff[RADIX];
-    __shared__ u64 s_base[RADIX];
-    __shared__ u32 s_nh[RADIX];
-    __shared__ u32 s_scan[NW];
-    __shared__ u64 s_scan64[NW];
-    __shared__ i64 s_p;
-
-    const int shift = pass * RADIX_BITS;
+    constexpr int NW = OsSmem<K, V>::NW;
+    __shared__ OsSmem<K, V> S;
     const bool next_hist = pass + 1 < C.passes;
-    const u32 lane = lane_id(), w = threadIdx.x >> 6;
-    const u32 tag = (u32)pass + 1;
     const i64 nparts = C.ppre[C.nseg];
-    const K *ckeys = (const K *)C.ck;
-    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) s_nh[d] = 0;
+    u32 *ticket = &C.counters[CNT_SORT + pass];
+    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) S.nh[d] = 0;
+    if (threadIdx.x == 0) S.p = (i64)atomicAdd(ticket, 1u);
+    __syncthreads();
+    i64 p = S.p;
     int cur_q = -1;
-    const i64 tb = C.tb_sort;
-    while (true) {
-        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_SORT + pass], 1u) * tb;
-        __syncthreads();
-        const i64 p0 = s_p;
-        if (p0 >= nparts) break;
-        __syncthreads();
-        for (i64 p = p0; p < min(p0 + tb, nparts); p++) {
-        for (int d = threadIdx.x; d < NW * RADIX; d += NTHREADS) (&s_wh[0][0])[d] = 0;
-        __syncthreads();
+    while (p < nparts) {
+        for (int d = threadIdx.x; d < NW * RADIX; d += NTHREADS) (&S.wh[0][0])[d] = 0;
         const int q = seg_search(C.ppre, C.nseg, p);
         if (q != cur_q) {
-            if (cur_q >= 0 && next_hist) hist_flush(C, s_nh, pass + 1, cur_q);
-            seg_digit_bases(C, pass, q, s_base, s_scan64);
+            __syncthreads();
+            if (cur_q >= 0 && next_hist) hist_flush(C, S.nh, pass + 1, cur_q);
+            seg_digit_bases(C, pass, q, S.base, S.scan64);
             cur_q = q;
         }
+        __syncthreads();
         const DevSeg &s = C.segs[q];
         const i64 first = C.ppre[q];
         const i64 c = p - first;
         const i64 n_q = C.dyn[q].n;
-        const i64 start = s.stage_base + c * PART;
         const int n = (int)min((i64)PART, n_q - c * PART);
-
-        // load, warp-striped: item k of lane l in wave w is w*64*IPT + k*64 + l
-        K key[IPT];
-        V val[IPT];
-        u32 rk[IPT];
-        u32 dg[IPT];
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-            if constexpr (GEN) {
-                const u32 x = (u32)(c * PART + idx);
-                key[k] = idx < n ? raw_key<K>(s, ckeys, x) : (K)0;
-                val[k] = (V)x;
-            } else {
-                key[k] = idx < n ? kin[start + idx] : (K)0;
-            }
-        }
-        if constexpr (!GEN) {
-            // payloads are only permuted: issue their loads now so they overlap the ranking
-#pragma unroll
-            for (int k = 0; k < IPT; k++) {
-                const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-                val[k] = idx < n ? vin[start + idx] : (V)0;
-            }
-        }
-        // per-wave stable ranking
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-            const bool valid = idx < n;
-            const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
-            u64 peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < RADIX_BITS; b++) {
-                const u64 m = __ballot((d >> b) & 1);
-                peers &= ((d >> b) & 1) ? m : ~m;
-            }
-            const u32 before = mbcnt(peers);
-            const u32 cnt = (u32)__popcll(peers);
-            u32 old = valid ? s_wh[w][d] : 0;
-            if (valid && before == 0) s_wh[w][d] = old + cnt;
-            rk[k] = old + before;
-            dg[k] = d;
-            if (next_hist && valid) atomicAdd(&s_nh[(u32)((key[k] >> (shift + RADIX_BITS)) & (RADIX - 1))], 1u);
-        }
-        __syncthreads();
-        // digit totals, wave prefixes, local digit offsets
-        const int d = threadIdx.x;  // RADIX == NTHREADS
-        u32 tot = 0;
-#pragma unroll
-        for (int ww = 0; ww < NW; ww++) {
-            u32 x = s_wh[ww][d];
-            s_wh[ww][d] = tot;
-            tot += x;
-        }
-        u32 all;
-        const u32 loff = block_excl_scan<u32>(tot, s_scan, all);
-        s_loff[d] = loff;
-        // product-wide offset of this digit in this partition
-        const u64 prefix = lookback_batched(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
-        s_goff[d] = (i64)(s_base[d] + prefix) - (i64)loff;
-        __syncthreads();
-        // scatter keys into LDS in sorted order
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-            if (idx < n) {
-                const u32 pos = s_loff[dg[k]] + s_wh[w][dg[k]] + rk[k];
-                rk[k] = pos;
-                s_buf.k[pos] = key[k];
-                s_dig[pos] = (unsigned char)dg[k];
-            }
-        }
-        __syncthreads();
-        const i64 lo = s.stage_base, hi = s.stage_base + n_q;
-        for (int i = threadIdx.x; i < n; i += NTHREADS) {
-            const i64 o = s_goff[s_dig[i]] + i;
-            if (o >= lo && o < hi) kout[o] = s_buf.k[i];
-            else atomicOr(&C.counters[CNT_ERR_SPIN], 2u);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-            if (idx < n) s_buf.v[rk[k]] = val[k];
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += NTHREADS) {
-            const i64 o = s_goff[s_dig[i]] + i;
-            if (o >= lo && o < hi) vout[o] = s_buf.v[i];
-        }
-        __syncthreads();
-        }
+        if (n == PART)
+            os_partition<K, V, GEN, true>(C, S, s, pass, p, first, c, n_q, n, kin, vin, kout, vout, next_hist, ticket);
+        else
+            os_partition<K, V, GEN, false>(C, S, s, pass, p, first, c, n_q, n, kin, vin, kout, vout, next_hist, ticket);
+        p = S.pn;
     }
     if (cur_q >= 0 && next_hist) {
         __syncthreads();
-        hist_flush(C, s_nh, pass + 1, cur_q);
+        hist_flush(C, S.nh, pass + 1, cur_q);
     }
 }
 
@@ -542,10 +571,14 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
 // thread that owns its first element, left to right in staging order (for
 // FP64 that is the row-major (i, j) order of the pp-matrix, as the sort is
 // stable and SEG_RAW items start in index order), continuing past the
-// thread's items and the partition end when the run does.  Non-zero sums get
-// their result position from a workgroup scan plus a look-back over the
-// product's earlier partitions; results are staged in LDS and written out
-// contiguously with the key decompressed to the packed exponent layout.
+// thread's items and the partition end when the run does.  Every run gets
+// the result slot given by its rank among the product's runs, which is known
+// from the keys alone: the partition publishes its run count before it
+// gathers the operands, and resolves its offset after summing.  A run whose
+// sum cancels to zero leaves a slot with a zero coefficient; k_zero_compact
+// removes those slots afterwards (only products that have any).  Results are
+// staged in LDS and written out contiguously with the key decompressed to the
+// packed exponent layout.
 // ---------------------------------------------------------------------------
 template <typename K, typename V, int RING>
 __device__ inline u64 item_value(const DevSeg &s, V v) {
@@ -558,104 +591,150 @@ __device__ inline u64 item_value(const DevSeg &s, V v) {
     }
 }
 
+constexpr u32 TAG_REDUCE = 200u, TAG_ZCOMPACT = 201u;
+
 template <typename K, typename V, int RING>
-__global__ __launch_bounds__(NTHREADS) void k_reduce(Ctx C, const K *__restrict__ kin, const V *__restrict__ vin) {
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_reduce(Ctx C, const K *__restrict__ kin, const V *__restrict__ vin) {
     constexpr int PADN = PART + PART / 16;
     __shared__ K s_k[PADN];
     __shared__ u64 s_v[PADN];
     __shared__ u32 s_scan[NTHREADS / 64];
-    __shared__ i64 s_p;
+    __shared__ i64 s_p, s_pn;
     __shared__ u64 s_base;
+    __shared__ u32 s_z;
     auto pad = [](int i) { return i + (i >> 4); };
     const i64 nparts = C.ppre[C.nseg];
-    const i64 tb = C.tb_sort;
-    while (true) {
-        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_REDUCE], 1u) * tb;
-        __syncthreads();
-        const i64 p0 = s_p;
-        if (p0 >= nparts) break;
-        __syncthreads();
-        for (i64 p = p0; p < min(p0 + tb, nparts); p++) {
+    u32 *ticket = &C.counters[CNT_REDUCE];
+    if (threadIdx.x == 0) s_p = (i64)atomicAdd(ticket, 1u);
+    __syncthreads();
+    i64 p = s_p;
+    while (p < nparts) {
         const int q = seg_search(C.ppre, C.nseg, p);
         const DevSeg &s = C.segs[q];
         const i64 first = C.ppre[q];
         const i64 c = p - first;
         const i64 n_q = C.dyn[q].n;
-        const i64 seg0 = s.stage_base;
-        const i64 start = seg0 + c * PART;
-        const i64 send = seg0 + n_q;
+        const i64 start = s.stage_base + c * PART;
+        const i64 send = s.stage_base + n_q;
         const int n = (int)min((i64)PART, n_q - c * PART);
-        for (int i = threadIdx.x; i < n; i += NTHREADS) {
-            s_k[pad(i)] = kin[start + i];
-            s_v[pad(i)] = item_value<K, V, RING>(s, vin[start + i]);
+        if (threadIdx.x == 0) s_z = 0;
+        // keys and raw payloads, register-blocked and coalesced
+        K kr[IPT];
+        V vr[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int i = (int)threadIdx.x + r * NTHREADS;
+            kr[r] = i < n ? kin[start + i] : (K)0;
+            vr[r] = i < n ? vin[start + i] : (V)0;
+        }
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int i = (int)threadIdx.x + r * NTHREADS;
+            if (i < n) s_k[pad(i)] = kr[r];
         }
         const K prevk = c > 0 ? kin[start - 1] : (K)0;
         __syncthreads();
-        // thread t owns items [t*IPT, t*IPT+IPT); a run's head sums the run
-        const int b0 = threadIdx.x * IPT;
-        u32 mask = 0;
-        K kprev = b0 == 0 ? prevk : s_k[pad(b0 - 1)];
-        bool have_prev = !(b0 == 0 && c == 0);
-        int open = -1;
-        u64 acc = 0;
+        // run heads among this thread's items [b0, b0 + IPT); publish the count
+        const int b0 = (int)threadIdx.x * IPT;
+        u32 hm = 0;
+        {
+            K kp = b0 == 0 ? prevk : s_k[pad(b0 > 0 ? b0 - 1 : 0)];
+            bool hp = !(b0 == 0 && c == 0);
 #pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int i = b0 + r;
-            if (i < n) {
-                const K key = s_k[pad(i)];
-                const u64 v = s_v[pad(i)];
-                const bool head = !have_prev || key != kprev;
-                if (head) {
-                    if (open >= 0) {
-                        s_v[pad(b0 + open)] = acc;
-                        if (!ring_is_zero<RING>(acc)) mask |= 1u << open;
-                    }
-                    open = r;
-                    acc = v;
-                } else if (open >= 0) {
-                    acc = ring_add<RING>(acc, v);
+            for (int r = 0; r < IPT; r++) {
+                if (b0 + r < n) {
+                    const K key = s_k[pad(b0 + r)];
+                    if (!hp || key != kp) hm |= 1u << r;
+                    kp = key;
+                    hp = true;
                 }
-                kprev = key;
-                have_prev = true;
             }
         }
-        if (open >= 0) {
-            // the last run may continue into the next threads' items and partitions
-            const K key = s_k[pad(b0 + open)];
-            int j = b0 + IPT;
-            while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
-            if (j >= n && n > 0) {
-                for (i64 g = start + n; g < send && kin[g] == key; g++)
-                    acc = ring_add<RING>(acc, item_value<K, V, RING>(s, vin[g]));
-            }
-            s_v[pad(b0 + open)] = acc;
-            if (!ring_is_zero<RING>(acc)) mask |= 1u << open;
-        }
-        const u32 cnt = (u32)__popc(mask);
         u32 total;
-        const u32 off = block_excl_scan<u32>(cnt, s_scan, total);
+        const u32 off = block_excl_scan<u32>((u32)__popc(hm), s_scan, total);
+        if (threadIdx.x == 0) lb_publish(C.look_red + p, first, p, TAG_REDUCE, total);
+        // item values: the operand gathers of all of a thread's items in flight together
+        {
+            u64 xv[IPT];
+            if constexpr (sizeof(V) == 8) {
+#pragma unroll
+                for (int r = 0; r < IPT; r++) xv[r] = (u64)vr[r];
+            } else {
+                u64 fa[IPT], gb[IPT];
+#pragma unroll
+                for (int r = 0; r < IPT; r++) {
+                    const int i = (int)threadIdx.x + r * NTHREADS;
+                    const u32 a = i < n ? div32((u32)vr[r], s.nb_div) : 0u;
+                    const u32 b = i < n ? (u32)vr[r] - a * (u32)s.nb : 0u;
+                    fa[r] = s.fc[a];
+                    gb[r] = s.gc[b];
+                }
+#pragma unroll
+                for (int r = 0; r < IPT; r++) xv[r] = ring_mul<RING>(fa[r], gb[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < IPT; r++) {
+                const int i = (int)threadIdx.x + r * NTHREADS;
+                if (i < n) s_v[pad(i)] = xv[r];
+            }
+        }
+        __syncthreads();
+        // each head sums its run; the sum replaces the head's value in LDS
+        {
+            int open = -1;
+            u64 acc = 0;
+#pragma unroll
+            for (int r = 0; r < IPT; r++) {
+                if (b0 + r < n) {
+                    const u64 v = s_v[pad(b0 + r)];
+                    if ((hm >> r) & 1) {
+                        if (open >= 0) s_v[pad(b0 + open)] = acc;
+                        open = r;
+                        acc = v;
+                    } else if (open >= 0) {
+                        acc = ring_add<RING>(acc, v);
+                    }
+                }
+            }
+            if (open >= 0) {
+                // the last run may continue into the next threads' items and partitions
+                const K key = s_k[pad(b0 + open)];
+                int j = b0 + IPT;
+                while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
+                if (j >= n && n > 0) {
+                    for (i64 g = start + n; g < send && kin[g] == key; g++)
+                        acc = ring_add<RING>(acc, item_value<K, V, RING>(s, vin[g]));
+                }
+                s_v[pad(b0 + open)] = acc;
+            }
+        }
+        // product-wide slot of this partition's first run
         if (threadIdx.x < 64) {
-            const u64 pre = lookback_wave(C.look_red, first, p, 200u, total, &C.counters[CNT_ERR_SPIN]);
+            const u64 pre = lookback_wave_resolve(C.look_red, first, p, TAG_REDUCE, total, &C.counters[CNT_ERR_SPIN]);
             if (threadIdx.x == 0) s_base = pre;
         }
-        // gather this thread's results, then stage them compacted in LDS
+        u32 tk = 0;
+        if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition
+        // gather this thread's runs, then stage them by slot in LDS
         K ok[IPT];
         u64 ov[IPT];
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
-            ok[r] = s_k[pad(b0 + r < PART ? b0 + r : 0)];
-            ov[r] = s_v[pad(b0 + r < PART ? b0 + r : 0)];
+            ok[r] = s_k[pad(b0 + r)];
+            ov[r] = s_v[pad(b0 + r)];
         }
         __syncthreads();
-        u32 o = off;
+        u32 o = off, zc = 0;
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
-            if (mask & (1u << r)) {
+            if ((hm >> r) & 1) {
                 s_k[o] = ok[r];
                 s_v[o] = ov[r];
+                zc += ring_is_zero<RING>(ov[r]) ? 1u : 0u;
                 o++;
             }
         }
+        if (zc) atomicAdd(&s_z, zc);
         __syncthreads();
         const u64 base = s_base;
         const VarParam *vp = C.vars + s.var_off;
@@ -666,9 +745,99 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(Ctx C, const K *__restrict_
                 s.hc[pos] = s_v[i];
             }
         }
-        if (c == C.dyn[q].nparts - 1 && threadIdx.x == 0) *s.n_out = (i64)(base + total);
-        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (c == C.dyn[q].nparts - 1) {
+                *s.n_out = (i64)(base + total);
+                C.dyn[q].heads = (i64)(base + total);
+            }
+            if (s_z) {
+                atomicAdd(&C.dyn[q].zeros, (unsigned long long)s_z);
+                atomicOr(&C.counters[CNT_ZEROS], 1u);
+            }
+            s_pn = (i64)tk;
         }
+        __syncthreads();
+        p = s_pn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_zero_compact: removes the cancelled (zero-coefficient) slots that
+// k_reduce left in the results of products that have any, in place and in
+// order.  Partition c of product q covers result slots [c*PART, (c+1)*PART)
+// up to min(heads, capacity).  A partition's writes land at or below its own
+// slots, and only after every earlier partition has published, i.e. read its
+// slots; so in-place compaction is safe.  When the slots exceed the capacity
+// (truncation), *n_out reports the slot count, which is the capacity that
+// avoids it, and the coefficients after the compacted prefix are zeroed.
+// ---------------------------------------------------------------------------
+template <int RING>
+__global__ __launch_bounds__(NTHREADS) void k_zero_compact(Ctx C) {
+    __shared__ u64 s_k[PART];
+    __shared__ u64 s_v[PART];
+    __shared__ u32 s_scan[NTHREADS / 64];
+    __shared__ i64 s_p;
+    __shared__ u64 s_base;
+    if (__hip_atomic_load(&C.counters[CNT_ZEROS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+    const i64 nparts = C.ppre[C.nseg];
+    while (true) {
+        if (threadIdx.x == 0) s_p = (i64)atomicAdd(&C.counters[CNT_ZCOMPACT], 1u);
+        __syncthreads();
+        const i64 p = s_p;
+        __syncthreads();
+        if (p >= nparts) break;
+        const int q = seg_search(C.ppre, C.nseg, p);
+        const DevSeg &s = C.segs[q];
+        if (C.dyn[q].zeros == 0) continue;
+        const i64 heads = C.dyn[q].heads;
+        const i64 lim = min(heads, s.cap);
+        const i64 first = C.ppre[q];
+        const i64 lo = (p - first) * PART;
+        if (lo >= lim) continue;
+        const int n = (int)min((i64)PART, lim - lo);
+        for (int i = threadIdx.x; i < n; i += NTHREADS) {
+            s_k[i] = s.hk[lo + i];
+            s_v[i] = s.hc[lo + i];
+        }
+        __syncthreads();
+        const int b0 = (int)threadIdx.x * IPT;
+        u64 kk[IPT], vv[IPT];
+        u32 m = 0;
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            kk[r] = s_k[b0 + r];
+            vv[r] = s_v[b0 + r];
+            if (b0 + r < n && !ring_is_zero<RING>(vv[r])) m |= 1u << r;
+        }
+        u32 total;
+        const u32 off = block_excl_scan<u32>((u32)__popc(m), s_scan, total);
+        if (threadIdx.x < 64) {
+            if (threadIdx.x == 0) lb_publish(C.look_red + p, first, p, TAG_ZCOMPACT, total);
+            const u64 pre = lookback_wave_resolve(C.look_red, first, p, TAG_ZCOMPACT, total, &C.counters[CNT_ERR_SPIN]);
+            if (threadIdx.x == 0) s_base = pre;
+        }
+        __syncthreads();
+        u32 o = off;
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            if ((m >> r) & 1) {
+                s_k[o] = kk[r];
+                s_v[o] = vv[r];
+                o++;
+            }
+        }
+        __syncthreads();
+        const u64 base = s_base;
+        for (int i = threadIdx.x; i < (int)total; i += NTHREADS) {
+            s.hk[base + i] = s_k[i];
+            s.hc[base + i] = s_v[i];
+        }
+        if (lo + n == lim) {
+            // last partition: clear the coefficients behind the compacted result
+            for (i64 i = (i64)(base + total) + threadIdx.x; i < lim; i += NTHREADS) s.hc[i] = 0;
+            if (threadIdx.x == 0) *s.n_out = heads > s.cap ? heads : (i64)(base + total);
+        }
+        __syncthreads();
     }
 }
 
@@ -906,9 +1075,13 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    ProfScope ps("reduce", st);
-    hipLaunchKernelGGL((k_reduce<K, V, RING>), dim3(grid_for(P.nparts_bound, cus * 2)), dim3(NTHREADS), 0, st, C,
-                       ka, va);
+    {
+        ProfScope ps("reduce", st);
+        hipLaunchKernelGGL((k_reduce<K, V, RING>), dim3(grid_for(P.nparts_bound, cus * 3)), dim3(NTHREADS), 0, st, C,
+                           ka, va);
+    }
+    ProfScope ps("zero_compact", st);
+    hipLaunchKernelGGL((k_zero_compact<RING>), dim3(grid_for(P.nparts_bound, cus * 2)), dim3(NTHREADS), 0, st, C);
 }
 
 template <typename K, int RING>

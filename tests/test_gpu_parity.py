@@ -164,6 +164,77 @@ def test_total_cancellation_gives_empty():
     assert hk.size == 0
 
 
+def _cancelling_pair(ring, n=1500, seed=31):
+    """f = p + q and g = p - q with p in x0..x2 and q in x3..x5 (disjoint
+    supports, no constant term): f*g = p^2 - q^2, and each of the n*n cross
+    monomials x^(a_i + b_j) gets exactly p_i*q_j - q_j*p_i = 0, which is an
+    exact zero in every ring (FP64 included: both products round the same)."""
+    rng = W.rng_for(seed)
+    lay = W.Layout(6, 10, ring)
+
+    def embed(part, lo):
+        e = W.unpack(part.keys, 3, 10)
+        e[:, 0] += 1
+        full = np.zeros((len(part), 6), dtype=np.int64)
+        full[:, lo:lo + 3] = e
+        return W.pack(full, 6, 10)
+
+    p = W.random_sparse(rng, n, 3, 10, 15, ring)
+    q = W.random_sparse(rng, n, 3, 10, 15, ring)
+    keys = np.concatenate([embed(p, 0), embed(q, 3)])
+    o = np.argsort(keys)
+    if ring == "modp":
+        neg_q = (P - q.coefs) % P
+    else:
+        neg_q = -q.coefs
+    f = W.Poly(lay, keys[o], np.concatenate([p.coefs, q.coefs])[o])
+    g = W.Poly(lay, keys[o], np.concatenate([p.coefs, neg_q])[o])
+    return f, g
+
+
+@pytest.mark.parametrize("ring", ["modp", "i64", "f64"])
+@pytest.mark.parametrize("mode", ["pairs", "combine", "intervals", "auto"])
+def test_cross_terms_cancel_on_sorted_path(ring, mode):
+    # about 2.25e6 result slots cancel, spread over every sort partition
+    pm = _pm()
+    pm.set_tuning(-1, {"pairs": 0, "combine": 1, "intervals": 2, "auto": -1}[mode], mode == "auto")
+    f, g = _cancelling_pair(ring)
+    want = oracle.mul(f, g)
+    assert len(want[0]) < len(f) * len(f) // 2
+    print(f"[parity] cancel {ring} {mode} na={len(f)} terms={len(want[0])}", flush=True)
+    assert_same(gpu_mul(f, g), want, ring, f"cancel {ring} {mode}")
+
+
+def test_cancellation_with_capacity_below_slots():
+    # capacity = the final term count, which is below the number of distinct
+    # monomials the sorted path sees before cancelled terms are dropped
+    pm = _pm()
+    pm.set_tuning(-1, 0, False)
+    f, g = _cancelling_pair("modp", n=600, seed=32)
+    wk, wc, _ = oracle.mul(f, g)
+    cnt = len(wk)
+    lay = (6, 10, "modp")
+    F, G = pm.to_device(f), pm.to_device(g)
+    out = pm.alloc_out(cnt, "modp")
+    h = pm.mul(lay, F, G, out=out)
+    assert h.n >= cnt
+    k = out[0].cpu().numpy().view(np.uint64)[:cnt]
+    c = out[1].cpu().numpy().view(np.uint64)[:cnt]
+    if h.n == cnt:
+        assert np.array_equal(k, wk) and np.array_equal(c, wc)
+    else:
+        # truncated: a prefix of the result, then zero coefficients
+        m = int(np.argmax(c == 0)) if np.any(c == 0) else cnt
+        assert np.all(c[m:] == 0)
+        assert np.array_equal(k[:m], wk[:m]) and np.array_equal(c[:m], wc[:m])
+    # a capacity of the reported size always suffices
+    out2 = pm.alloc_out(max(h.n, cnt), "modp")
+    h2 = pm.mul(lay, F, G, out=out2)
+    assert h2.n == cnt
+    got = h2.numpy()
+    assert np.array_equal(got[0], wk) and np.array_equal(got[1], wc)
+
+
 def test_single_variable_full_width():
     # one variable, 64-bit field: the degree box is not compressible
     rng = np.random.default_rng(5)
