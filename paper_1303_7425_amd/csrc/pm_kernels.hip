@@ -26,60 +26,89 @@ namespace pm {
 // k_stats: one workgroup per (segment, operand side).  Per-variable min/max of
 // the exponents, strict ascending order, key bits outside the fields, and
 // coefficient range.  out[(q*2+side)*2*nvars + v] = min, [... + nvars + v] = max.
+// One sweep over the terms per group of eight variables, four independent
+// loads in flight per thread; the checks ride along with the first group.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTHREADS) void k_stats(const DevSeg *segs, int nvars, int bits, int ring, u64 *out,
                                                      u32 *flags) {
+    constexpr int G = 8, U = 4, NW = NTHREADS / 64;
     const int q = blockIdx.x >> 1, side = blockIdx.x & 1;
-    const DevSeg s = segs[q];
+    const DevSeg &s = segs[q];
     const i64 n = side ? s.nb : s.na;
     const u64 *k = side ? s.gk : s.fk;
     const u64 *c = side ? s.gc : s.fc;
     const u64 mask = bits == 64 ? ~0ull : ((1ull << bits) - 1);
     const int used = nvars * bits;
-    __shared__ u64 s_mn[NTHREADS / 64], s_mx[NTHREADS / 64];
+    __shared__ u64 s_mn[G][NW], s_mx[G][NW];
     __shared__ u32 s_flag;
     if (threadIdx.x == 0) s_flag = 0;
     __syncthreads();
     u32 fl = 0;
-    for (i64 i = threadIdx.x; i < n; i += NTHREADS) {
-        u64 key = k[i];
-        if (used < 64 && (key >> used) != 0) fl |= ST_BADBITS;
-        if (i > 0 && !(key > k[i - 1])) fl |= ST_UNSORTED;
-        u64 cv = c[i];
-        if (ring == RING_MODP && cv >= P61) fl |= ST_RANGE;
-        if (ring == RING_F64 && ((cv >> 52) & 0x7ff) == 0x7ff) fl |= ST_RANGE;
-    }
-    if (fl) atomicOr(&s_flag, fl);
     u64 *o = out + (i64)(q * 2 + side) * 2 * nvars;
-    for (int v = 0; v < nvars; v++) {
-        const u32 sh = (u32)((nvars - 1 - v) * bits);
-        u64 mn = ~0ull, mx = 0;
-        for (i64 i = threadIdx.x; i < n; i += NTHREADS) {
-            u64 e = (k[i] >> sh) & mask;
-            mn = e < mn ? e : mn;
-            mx = e > mx ? e : mx;
+    for (int v0 = 0; v0 < nvars; v0 += G) {
+        u64 mn[G], mx[G];
+        u32 sh[G];
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            mn[u] = ~0ull;
+            mx[u] = 0;
+            sh[u] = v0 + u < nvars ? (u32)((nvars - 1 - (v0 + u)) * bits) : 0u;
+        }
+        for (i64 i0 = threadIdx.x; i0 < n; i0 += U * NTHREADS) {
+            u64 kk[U], kp[U], cc[U];
+#pragma unroll
+            for (int r = 0; r < U; r++) {
+                const i64 i = i0 + (i64)r * NTHREADS;
+                kk[r] = i < n ? k[i] : 0;
+                kp[r] = (v0 == 0 && i > 0 && i < n) ? k[i - 1] : 0;
+                cc[r] = (v0 == 0 && i < n) ? c[i] : 0;
+            }
+#pragma unroll
+            for (int r = 0; r < U; r++) {
+                const i64 i = i0 + (i64)r * NTHREADS;
+                if (i >= n) continue;
+                if (v0 == 0) {
+                    if (used < 64 && (kk[r] >> used) != 0) fl |= ST_BADBITS;
+                    if (i > 0 && !(kk[r] > kp[r])) fl |= ST_UNSORTED;
+                    if (ring == RING_MODP && cc[r] >= P61) fl |= ST_RANGE;
+                    if (ring == RING_F64 && ((cc[r] >> 52) & 0x7ff) == 0x7ff) fl |= ST_RANGE;
+                }
+#pragma unroll
+                for (int u = 0; u < G; u++) {
+                    const u64 e = (kk[r] >> sh[u]) & mask;
+                    mn[u] = e < mn[u] ? e : mn[u];
+                    mx[u] = e > mx[u] ? e : mx[u];
+                }
+            }
         }
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-            u64 a = __shfl_xor(mn, d, 64), b = __shfl_xor(mx, d, 64);
-            mn = a < mn ? a : mn;
-            mx = b > mx ? b : mx;
-        }
-        if (lane_id() == 0) {
-            s_mn[threadIdx.x >> 6] = mn;
-            s_mx[threadIdx.x >> 6] = mx;
+        for (int u = 0; u < G; u++) {
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const u64 a = __shfl_xor(mn[u], d, 64), b = __shfl_xor(mx[u], d, 64);
+                mn[u] = a < mn[u] ? a : mn[u];
+                mx[u] = b > mx[u] ? b : mx[u];
+            }
+            if (lane_id() == 0) {
+                s_mn[u][threadIdx.x >> 6] = mn[u];
+                s_mx[u][threadIdx.x >> 6] = mx[u];
+            }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int w = 1; w < NTHREADS / 64; w++) {
-                mn = s_mn[w] < mn ? s_mn[w] : mn;
-                mx = s_mx[w] > mx ? s_mx[w] : mx;
+        if (threadIdx.x < G && v0 + (int)threadIdx.x < nvars) {
+            const int u = threadIdx.x;
+            u64 a = s_mn[u][0], b = s_mx[u][0];
+            for (int w = 1; w < NW; w++) {
+                a = s_mn[u][w] < a ? s_mn[u][w] : a;
+                b = s_mx[u][w] > b ? s_mx[u][w] : b;
             }
-            o[v] = mn;
-            o[nvars + v] = mx;
+            o[v0 + u] = a;
+            o[nvars + v0 + u] = b;
         }
         __syncthreads();
     }
+    if (fl) atomicOr(&s_flag, fl);
+    __syncthreads();
     if (threadIdx.x == 0) flags[q * 2 + side] = s_flag;
 }
 
@@ -302,6 +331,46 @@ __device__ inline K raw_key(const DevSeg &s, const K *ck, u32 x) {
     return ck[s.ck_f + i] + ck[s.ck_g + j];
 }
 
+// Wave-uniform value held in scalar registers.
+__device__ inline i64 uniform64(i64 v) {
+    const u32 lo = __builtin_amdgcn_readfirstlane((u32)(u64)v);
+    const u32 hi = __builtin_amdgcn_readfirstlane((u32)((u64)v >> 32));
+    return (i64)(((u64)hi << 32) | lo);
+}
+__device__ inline u32 uniform32(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The fields of one product that a sort pass uses, kept in registers while
+// consecutive partitions belong to the same product.
+struct OsSeg {
+    i64 first, n_q, lo;
+    i64 ck_f, ck_g;
+    u32 nb;
+    Div32 nb_div;
+};
+
+__device__ inline OsSeg load_os_seg(const Ctx &C, int q) {
+    const DevSeg &s = C.segs[q];
+    OsSeg r;
+    r.first = uniform64(C.ppre[q]);
+    r.n_q = uniform64(C.dyn[q].n);
+    r.lo = uniform64(s.stage_base);
+    r.ck_f = uniform64(s.ck_f);
+    r.ck_g = uniform64(s.ck_g);
+    r.nb = uniform32((u32)s.nb);
+    r.nb_div.m = uniform32(s.nb_div.m);
+    r.nb_div.s1 = uniform32(s.nb_div.s1);
+    r.nb_div.s2 = uniform32(s.nb_div.s2);
+    r.nb_div.d = uniform32(s.nb_div.d);
+    return r;
+}
+
+template <typename K>
+__device__ inline K raw_key_os(const OsSeg &s, const K *ck, u32 x) {
+    const u32 i = div32(x, s.nb_div);
+    const u32 j = x - i * s.nb;
+    return ck[s.ck_f + i] + ck[s.ck_g + j];
+}
+
 template <typename K>
 __global__ __launch_bounds__(NTHREADS) void k_hist_raw(Ctx C) {
     __shared__ u32 s_h[RADIX];
@@ -409,17 +478,27 @@ struct OsSmem {
     i64 p, pn;
 };
 
-template <typename K, typename V, bool GEN, bool FULL>
-__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const DevSeg &s, int pass, i64 p, i64 first,
-                                             i64 c, i64 n_q, int n, const K *__restrict__ kin,
+// Items past the end of a partial partition carry the all-ones key: they rank
+// last in the last digit, i.e. at sorted positions [n, PART), so the valid
+// items' positions are unaffected; only that digit's published count and the
+// global writes account for them.
+template <typename K, typename V, bool GEN>
+__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, i64 p, i64 first,
+                                             i64 c, i64 lo, i64 span, int n, const K *__restrict__ kin,
                                              const V *__restrict__ vin, K *__restrict__ kout, V *__restrict__ vout,
                                              bool next_hist, u32 *ticket) {
     constexpr int NW = OsSmem<K, V>::NW;
     const int shift = pass * RADIX_BITS;
-    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    // an opaque copy of the thread index: keeps the per-item index and
+    // address arithmetic inside the partition loop instead of holding sixteen
+    // of each in registers for the whole kernel
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const u32 lane = (u32)tid & 63u, w = (u32)tid >> 6;
     const u32 tag = (u32)pass + 1;
-    const i64 start = s.stage_base + c * PART;
+    const i64 start = lo + c * PART;
     const K *ckeys = (const K *)C.ck;
+    const int wbase = (int)w * 64 * IPT + (int)lane;
 
     // load, warp-striped: item k of lane l in wave w is w*64*IPT + k*64 + l
     K key[IPT];
@@ -427,45 +506,43 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const DevS
     u32 rk[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
-        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
+        const int idx = wbase + k * 64;
         if constexpr (GEN) {
             const u32 x = (u32)(c * PART + idx);
-            key[k] = (FULL || idx < n) ? raw_key<K>(s, ckeys, x) : (K)0;
+            key[k] = idx < n ? raw_key_os<K>(s, ckeys, x) : ~(K)0;
             val[k] = (V)x;
         } else {
-            key[k] = (FULL || idx < n) ? kin[start + idx] : (K)0;
+            key[k] = idx < n ? kin[start + idx] : ~(K)0;
         }
     }
     if constexpr (!GEN) {
         // payloads are only permuted: issue their loads now so they overlap the ranking
 #pragma unroll
         for (int k = 0; k < IPT; k++) {
-            const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-            val[k] = (FULL || idx < n) ? vin[start + idx] : (V)0;
+            const int idx = wbase + k * 64;
+            val[k] = idx < n ? vin[start + idx] : (V)0;
         }
     }
     // per-wave stable ranking
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
-        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-        const bool valid = FULL || idx < n;
         const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
-        u64 peers = FULL ? ~0ull : __ballot(valid);
+        u64 peers = ~0ull;
 #pragma unroll
         for (int b = 0; b < RADIX_BITS; b++) {
             const u64 m = __ballot((d >> b) & 1);
             peers &= ((d >> b) & 1) ? m : ~m;
         }
         const u32 before = mbcnt(peers);
-        const u32 cnt = (u32)__popcll(peers);
-        const u32 old = valid ? S.wh[w][d] : 0;
-        if (valid && before == 0) S.wh[w][d] = old + cnt;
+        const u32 old = S.wh[w][d];
+        if (before == 0) S.wh[w][d] = old + (u32)__popcll(peers);
         rk[k] = old + before;
-        if (next_hist && valid) atomicAdd(&S.nh[(u32)((key[k] >> (shift + RADIX_BITS)) & (RADIX - 1))], 1u);
+        if (next_hist && wbase + k * 64 < n)
+            atomicAdd(&S.nh[(u32)((key[k] >> (shift + RADIX_BITS)) & (RADIX - 1))], 1u);
     }
     __syncthreads();
     // digit totals, wave prefixes, local digit offsets; publish the totals
-    const int d = threadIdx.x;  // RADIX == NTHREADS
+    const int d = tid;  // RADIX == NTHREADS
     u32 tot = 0;
 #pragma unroll
     for (int ww = 0; ww < NW; ww++) {
@@ -473,22 +550,20 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const DevS
         S.wh[ww][d] = tot;
         tot += x;
     }
-    lb_publish(C.look + p * RADIX + d, first, p, tag, tot);
     u32 all;
     const u32 loff = block_excl_scan<u32>(tot, S.scan, all);
+    if (d == RADIX - 1) tot -= (u32)(PART - n);
+    lb_publish(C.look + p * RADIX + d, first, p, tag, tot);
     S.loff[d] = loff;
     __syncthreads();
     // keys into LDS in sorted order
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
-        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-        if (FULL || idx < n) {
-            const u32 dk = (u32)((key[k] >> shift) & (RADIX - 1));
-            const u32 pos = S.loff[dk] + S.wh[w][dk] + rk[k];
-            rk[k] = pos;
-            S.buf.k[pos] = key[k];
-            S.dig[pos] = (unsigned char)dk;
-        }
+        const u32 dk = (u32)((key[k] >> shift) & (RADIX - 1));
+        const u32 pos = S.loff[dk] + S.wh[w][dk] + rk[k];
+        rk[k] = pos;
+        S.buf.k[pos] = key[k];
+        S.dig[pos] = (unsigned char)dk;
     }
     // product-wide offset of this digit in this partition
     const u64 prefix = lookback_batched_resolve(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
@@ -496,31 +571,30 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const DevS
     u32 tk = 0;
     if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition, claimed while this one scatters
     __syncthreads();
-    const i64 lo = s.stage_base, span = n_q;
+    bool bad = false;
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
-        const int i = (int)threadIdx.x + k * NTHREADS;
-        if (FULL || i < n) {
+        const int i = tid + k * NTHREADS;
+        if (i < n) {
             const i64 o = S.goff[S.dig[i]] + i;
-            if ((u64)(o - lo) < (u64)span) kout[o] = S.buf.k[i];
-            else atomicOr(&C.counters[CNT_ERR_SPIN], 2u);
+            const bool ok = (u64)(o - lo) < (u64)span;
+            if (ok) kout[o] = S.buf.k[i];
+            bad |= !ok;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
-        const int idx = (int)w * 64 * IPT + k * 64 + (int)lane;
-        if (FULL || idx < n) S.buf.v[rk[k]] = val[k];
-    }
+    for (int k = 0; k < IPT; k++) S.buf.v[rk[k]] = val[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
-        const int i = (int)threadIdx.x + k * NTHREADS;
-        if (FULL || i < n) {
+        const int i = tid + k * NTHREADS;
+        if (i < n) {
             const i64 o = S.goff[S.dig[i]] + i;
             if ((u64)(o - lo) < (u64)span) vout[o] = S.buf.v[i];
         }
     }
+    if (bad) atomicOr(&C.counters[CNT_ERR_SPIN], 2u);
     if (threadIdx.x == 0) S.pn = (i64)tk;
     __syncthreads();
 }
@@ -539,25 +613,24 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
     __syncthreads();
     i64 p = S.p;
     int cur_q = -1;
+    OsSeg sq{};
     while (p < nparts) {
         for (int d = threadIdx.x; d < NW * RADIX; d += NTHREADS) (&S.wh[0][0])[d] = 0;
-        const int q = seg_search(C.ppre, C.nseg, p);
+        // partitions come in queue order: the current product still holds p
+        // unless p has reached the next product's first partition
+        const int q = (cur_q >= 0 && p < sq.first + (sq.n_q + PART - 1) / PART) ? cur_q : seg_search(C.ppre, C.nseg, p);
         if (q != cur_q) {
             __syncthreads();
             if (cur_q >= 0 && next_hist) hist_flush(C, S.nh, pass + 1, cur_q);
             seg_digit_bases(C, pass, q, S.base, S.scan64);
+            sq = load_os_seg(C, q);
             cur_q = q;
         }
         __syncthreads();
-        const DevSeg &s = C.segs[q];
-        const i64 first = C.ppre[q];
-        const i64 c = p - first;
-        const i64 n_q = C.dyn[q].n;
-        const int n = (int)min((i64)PART, n_q - c * PART);
-        if (n == PART)
-            os_partition<K, V, GEN, true>(C, S, s, pass, p, first, c, n_q, n, kin, vin, kout, vout, next_hist, ticket);
-        else
-            os_partition<K, V, GEN, false>(C, S, s, pass, p, first, c, n_q, n, kin, vin, kout, vout, next_hist, ticket);
+        const i64 c = p - sq.first;
+        const int n = (int)min((i64)PART, sq.n_q - c * PART);
+        os_partition<K, V, GEN>(C, S, sq, pass, p, sq.first, c, sq.lo, sq.n_q, n, kin, vin, kout, vout, next_hist,
+                                ticket);
         p = S.pn;
     }
     if (cur_q >= 0 && next_hist) {
@@ -591,6 +664,57 @@ __device__ inline u64 item_value(const DevSeg &s, V v) {
     }
 }
 
+// The fields of one product that the reduction uses, kept in scalar
+// registers while consecutive partitions belong to the same product.
+struct RdSeg {
+    i64 first, n_q, lo, nparts, cap, var_off;
+    const u64 *fc, *gc;
+    u64 *hk, *hc;
+    i64 *n_out;
+    u64 lo_key;
+    u32 nb;
+    Div32 nb_div;
+};
+
+template <typename T>
+__device__ inline T *uniform_ptr(T *p) {
+    return (T *)(uintptr_t)uniform64((i64)(uintptr_t)p);
+}
+
+__device__ inline RdSeg load_rd_seg(const Ctx &C, int q) {
+    const DevSeg &s = C.segs[q];
+    RdSeg r;
+    r.first = uniform64(C.ppre[q]);
+    r.n_q = uniform64(C.dyn[q].n);
+    r.nparts = uniform64(C.dyn[q].nparts);
+    r.lo = uniform64(s.stage_base);
+    r.cap = uniform64(s.cap);
+    r.var_off = uniform64(s.var_off);
+    r.fc = uniform_ptr(s.fc);
+    r.gc = uniform_ptr(s.gc);
+    r.hk = uniform_ptr(s.hk);
+    r.hc = uniform_ptr(s.hc);
+    r.n_out = uniform_ptr(s.n_out);
+    r.lo_key = (u64)uniform64((i64)s.lo_key);
+    r.nb = uniform32((u32)s.nb);
+    r.nb_div.m = uniform32(s.nb_div.m);
+    r.nb_div.s1 = uniform32(s.nb_div.s1);
+    r.nb_div.s2 = uniform32(s.nb_div.s2);
+    r.nb_div.d = uniform32(s.nb_div.d);
+    return r;
+}
+
+template <typename K, typename V, int RING>
+__device__ inline u64 item_value_rd(const RdSeg &s, V v) {
+    if constexpr (sizeof(V) == 8) {
+        return (u64)v;
+    } else {
+        const u32 i = div32((u32)v, s.nb_div);
+        const u32 j = (u32)v - i * s.nb;
+        return ring_mul<RING>(s.fc[i], s.gc[j]);
+    }
+}
+
 constexpr u32 TAG_REDUCE = 200u, TAG_ZCOMPACT = 201u;
 
 template <typename K, typename V, int RING>
@@ -608,34 +732,41 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
     if (threadIdx.x == 0) s_p = (i64)atomicAdd(ticket, 1u);
     __syncthreads();
     i64 p = s_p;
+    int q = -1;
+    RdSeg s{};
     while (p < nparts) {
-        const int q = seg_search(C.ppre, C.nseg, p);
-        const DevSeg &s = C.segs[q];
-        const i64 first = C.ppre[q];
+        if (q < 0 || p >= s.first + s.nparts) {
+            q = seg_search(C.ppre, C.nseg, p);
+            s = load_rd_seg(C, q);
+        }
+        const i64 first = s.first;
         const i64 c = p - first;
-        const i64 n_q = C.dyn[q].n;
-        const i64 start = s.stage_base + c * PART;
-        const i64 send = s.stage_base + n_q;
+        const i64 n_q = s.n_q;
+        const i64 start = s.lo + c * PART;
+        const i64 send = s.lo + n_q;
         const int n = (int)min((i64)PART, n_q - c * PART);
         if (threadIdx.x == 0) s_z = 0;
+        // opaque thread index: per-item index arithmetic stays in the loop
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
         // keys and raw payloads, register-blocked and coalesced
         K kr[IPT];
         V vr[IPT];
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
-            const int i = (int)threadIdx.x + r * NTHREADS;
+            const int i = tid + r * NTHREADS;
             kr[r] = i < n ? kin[start + i] : (K)0;
             vr[r] = i < n ? vin[start + i] : (V)0;
         }
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
-            const int i = (int)threadIdx.x + r * NTHREADS;
+            const int i = tid + r * NTHREADS;
             if (i < n) s_k[pad(i)] = kr[r];
         }
         const K prevk = c > 0 ? kin[start - 1] : (K)0;
         __syncthreads();
         // run heads among this thread's items [b0, b0 + IPT); publish the count
-        const int b0 = (int)threadIdx.x * IPT;
+        const int b0 = tid * IPT;
         u32 hm = 0;
         {
             K kp = b0 == 0 ? prevk : s_k[pad(b0 > 0 ? b0 - 1 : 0)];
@@ -663,7 +794,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
                 u64 fa[IPT], gb[IPT];
 #pragma unroll
                 for (int r = 0; r < IPT; r++) {
-                    const int i = (int)threadIdx.x + r * NTHREADS;
+                    const int i = tid + r * NTHREADS;
                     const u32 a = i < n ? div32((u32)vr[r], s.nb_div) : 0u;
                     const u32 b = i < n ? (u32)vr[r] - a * (u32)s.nb : 0u;
                     fa[r] = s.fc[a];
@@ -674,7 +805,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
             }
 #pragma unroll
             for (int r = 0; r < IPT; r++) {
-                const int i = (int)threadIdx.x + r * NTHREADS;
+                const int i = tid + r * NTHREADS;
                 if (i < n) s_v[pad(i)] = xv[r];
             }
         }
@@ -703,7 +834,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
                 while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
                 if (j >= n && n > 0) {
                     for (i64 g = start + n; g < send && kin[g] == key; g++)
-                        acc = ring_add<RING>(acc, item_value<K, V, RING>(s, vin[g]));
+                        acc = ring_add<RING>(acc, item_value_rd<K, V, RING>(s, vin[g]));
                 }
                 s_v[pad(b0 + open)] = acc;
             }
@@ -746,7 +877,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
             }
         }
         if (threadIdx.x == 0) {
-            if (c == C.dyn[q].nparts - 1) {
+            if (c == s.nparts - 1) {
                 *s.n_out = (i64)(base + total);
                 C.dyn[q].heads = (i64)(base + total);
             }
