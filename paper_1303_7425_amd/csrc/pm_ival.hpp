@@ -372,9 +372,13 @@ __global__ __launch_bounds__(NTHREADS) void k_ival(Ctx C) {
                     __syncthreads();
                 }
                 if (threadIdx.x == 0 && have && !ring_is_zero<RING>(acc)) {
-                    const u64 slot = (u64)s.stage_base + s_ob + s_run;
-                    ((K *)C.stB_k)[slot] = klo;
-                    ((u64 *)C.stB_v)[slot] = acc;
+                    const u64 rel = s_ob + s_run;
+                    if ((i64)rel < s.stage_bound) {
+                        ((K *)C.stB_k)[(u64)s.stage_base + rel] = klo;
+                        ((u64 *)C.stB_v)[(u64)s.stage_base + rel] = acc;
+                    } else {
+                        atomicOr(&C.counters[CNT_ERR_SPIN], 16u);
+                    }
                     s_run = s_run + 1;
                 }
                 __syncthreads();
@@ -450,15 +454,21 @@ __global__ __launch_bounds__(NTHREADS) void k_ival(Ctx C) {
             }
             u32 rt;
             const u32 ro = block_excl_scan<u32>((u32)__popc(mask), s_scan, rt);
-            const u64 slot0 = (u64)s.stage_base + s_ob + s_run + ro;
+            const u64 rel0 = s_ob + s_run + ro;
             u32 w = 0;
+            bool over = false;
             for (int r = 0; r < IPT; r++) {
                 if (mask & (1u << r)) {
-                    ((K *)C.stB_k)[slot0 + w] = klo + (K)s_k[i0 + r];
-                    ((u64 *)C.stB_v)[slot0 + w] = s_v[i0 + r];
+                    if ((i64)(rel0 + w) < s.stage_bound) {
+                        ((K *)C.stB_k)[(u64)s.stage_base + rel0 + w] = klo + (K)s_k[i0 + r];
+                        ((u64 *)C.stB_v)[(u64)s.stage_base + rel0 + w] = s_v[i0 + r];
+                    } else {
+                        over = true;
+                    }
                     w++;
                 }
             }
+            if (over) atomicOr(&C.counters[CNT_ERR_SPIN], 16u);
             __syncthreads();
             if (threadIdx.x == 0) s_run = s_run + rt;
             __syncthreads();
@@ -508,9 +518,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ival_copy(Ctx C) {
         const IvalItem I = C.iv_items_arr[it];
         const u64 dst = C.iv_off[it];
         const VarParam *vp = C.vars + s.var_off;
+        const u64 send = (u64)s.stage_base + (u64)s.stage_bound;
         for (u64 e = threadIdx.x; e < I.ocount; e += NTHREADS) {
             const u64 pos = dst + e;
-            if ((i64)pos < s.cap) {
+            if ((i64)pos < s.cap && I.ostart + e < send) {
                 s.hk[pos] = decompress<K>(((const K *)C.stB_k)[I.ostart + e], vp, C.nvars, s.lo_key);
                 s.hc[pos] = ((const u64 *)C.stB_v)[I.ostart + e];
             }
