@@ -38,6 +38,79 @@ def measured_traffic(label):
     return None if e is None else e["fetch_bytes"] + e["write_bytes"]
 
 
+# rocprofv3 kernel names -> the labels used in the summaries
+KERNEL_LABELS = [
+    ("k_onesweep<unsigned int, unsigned int, false>", "onesweep pass (reads staged items)"),
+    ("k_onesweep<unsigned int, unsigned int, true>", "onesweep pass 0 (generates items)"),
+    ("k_reduce<", "reduce"),
+    ("k_zero_compact<", "zero_compact"),
+    ("k_hist_raw<", "hist_raw"),
+    ("k_seg_prepare", "seg_prepare"),
+    ("k_stats", "stats"),
+    ("k_compress<", "compress"),
+    ("k_fill", "fill"),
+]
+
+
+def kernel_label(name):
+    for key, label in KERNEL_LABELS:
+        if key in name:
+            return label
+    return None
+
+
+def traffic_summary(fetch_csv, write_csv):
+    """rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of a
+    `bench.py --copy-calibration` run -> per-launch HBM bytes, each counter
+    scaled by what it reads for the 512 MiB calibration copies; writes the
+    JSON that the roofline's `traffic` field is taken from and prints a table."""
+    import csv
+    import hashlib
+    from collections import defaultdict
+
+    def load(path, counter):
+        per = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                per[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
+        return per
+
+    fe, wr = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    cal = float(1 << 29)
+    fetch_scale = cal / max(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)
+    write_scale = cal / max(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)
+    per = {}
+    for name, vs in fe.items():
+        label = kernel_label(name)
+        if label is None or name not in wr:
+            continue
+        per[label] = {"fetch_bytes": sum(vs) / len(vs) * fetch_scale,
+                      "write_bytes": sum(wr[name]) / len(wr[name]) * write_scale, "launches": len(vs)}
+    src = os.path.join(ROOT, "paper_1303_7425_amd", "csrc", "pm_kernels.hip")
+    out = {"kernel_source_sha256_16": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16],
+           "workload": "sparse 5-var n=12 mod p", "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "per_launch": per}
+    with open(TRAFFIC_PROFILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"fetch scale {fetch_scale:.4f}, write scale {write_scale:.4f}, kernel source {out['kernel_source_sha256_16']}")
+    print("| kernel | launches | read MB (scaled) | write MB (scaled) |")
+    print("|---|---|---|---|")
+    for label, e in sorted(per.items(), key=lambda kv: -(kv[1]["fetch_bytes"] + kv[1]["write_bytes"])):
+        print(f"| {label} | {e['launches']} | {e['fetch_bytes'] / 1e6:.1f} | {e['write_bytes'] / 1e6:.1f} |")
+
+
+def trace_summary(stats_csv):
+    """rocprofv3 --kernel-trace --stats kernel_stats.csv -> markdown table."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    print("| kernel | calls | average us | share of GPU time |")
+    print("|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        print(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+              f"{100.0 * float(r['TotalDurationNs']) / tot:.1f}% |")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +125,10 @@ def parse():
                          "arrivals through the continuous-batching server")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 512 MiB three times (counter scaling for HBM traffic)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarize rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs (no GPU needed)")
+    ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV",
+                    help="summarize a rocprofv3 --stats kernel_stats.csv (no GPU needed)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--wave-gib", type=float, default=96.0, help="HBM per memory wave (outputs + workspace)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -193,6 +270,12 @@ def bench_serve(args):
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the product path is single-GPU in this "
               "build, see DESIGN.md for how it would shard", file=sys.stderr)
