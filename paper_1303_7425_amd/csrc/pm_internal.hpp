@@ -30,6 +30,7 @@ constexpr int IV_SAMPLES_MAX = 4096;   // grid samples per product ((l+1)^2, l <
 constexpr int NTHREADS = 256;          // threads per workgroup (4 wave64s)
 constexpr int IPT = 16;                // items per thread in sort / reduce partitions
 constexpr int PART = NTHREADS * IPT;   // items per partition
+constexpr int SCAN_CH = 32;            // partitions per chunk of the partition-offset scan
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
@@ -125,6 +126,10 @@ struct Ctx {
     u64 *box;
     unsigned long long *hist;   // [passes][nseg][RADIX] digit counts per product
     u64 *look;                  // sort lookback [nparts_bound][RADIX]
+    u64 *pcnt;                  // per-partition digit counts, then offsets [nparts_bound][RADIX]
+    u64 *ctot;                  // per-chunk digit totals, then offsets [nchunks][RADIX]
+    i64 *chpre;                 // [nseg+1] chunk prefix over products (device computed)
+    u64 *pbase;                 // [nseg][RADIX] digit bases of the partition-offset scan
     u64 *look_red;              // reduce lookback [nparts_bound]
     u64 *look_cmp;              // dense compaction lookback [ndparts]
     u64 *look_tile;             // staging offsets of combined tiles [ntiles]

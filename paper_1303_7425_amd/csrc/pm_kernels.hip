@@ -322,7 +322,9 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
 // ---------------------------------------------------------------------------
 // SEG_RAW products: pair (i, j) of the pp-matrix has index x = i*nb + j; the
 // sort carries (key, x) and the reduction regenerates a_i * b_j from x.
-// k_hist_raw: digit-0 histogram of every pair key, generated on the fly.
+// k_hist_raw: digit-0 counts of every sort partition (pcnt), keys generated
+// on the fly; the partition-offset scan turns them into the generating pass's
+// scatter offsets, so that pass needs no look-back.
 // ---------------------------------------------------------------------------
 template <typename K>
 __device__ inline K raw_key(const DevSeg &s, const K *ck, u32 x) {
@@ -374,31 +376,33 @@ __device__ inline K raw_key_os(const OsSeg &s, const K *ck, u32 x) {
 template <typename K>
 __global__ __launch_bounds__(NTHREADS) void k_hist_raw(Ctx C) {
     __shared__ u32 s_h[RADIX];
-    __shared__ i64 s_p;
-    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) s_h[d] = 0;
-    int cur_q = -1;
     const i64 nparts = C.ppre[C.nseg];
     const K *ck = (const K *)C.ck;
-    (void)s_p;
+    int cur_q = -1;
+    OsSeg sq{};
     for (i64 p = blockIdx.x; p < nparts; p += gridDim.x) {
-        const int q = seg_search(C.ppre, C.nseg, p);
+        s_h[threadIdx.x] = 0;  // RADIX == NTHREADS
+        const int q = (cur_q >= 0 && p < sq.first + (sq.n_q + PART - 1) / PART) ? cur_q : seg_search(C.ppre, C.nseg, p);
         if (q != cur_q) {
-            __syncthreads();
-            if (cur_q >= 0) hist_flush(C, s_h, 0, cur_q);
-            __syncthreads();
+            sq = load_os_seg(C, q);
             cur_q = q;
         }
-        const DevSeg &s = C.segs[q];
-        const i64 c = p - C.ppre[q];
-        const i64 n_q = C.dyn[q].n;
-        const int n = (int)min((i64)PART, n_q - c * PART);
-        const u32 x0 = (u32)(c * PART);
-        for (int e = threadIdx.x; e < n; e += NTHREADS)
-            atomicAdd(&s_h[(u32)raw_key<K>(s, ck, x0 + e) & (RADIX - 1)], 1u);
-    }
-    if (cur_q >= 0) {
         __syncthreads();
-        hist_flush(C, s_h, 0, cur_q);
+        const i64 c = p - sq.first;
+        const int n = (int)min((i64)PART, sq.n_q - c * PART);
+        const u32 x0 = (u32)(c * PART);
+        K key[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            const int idx = (int)threadIdx.x + k * NTHREADS;
+            key[k] = idx < n ? raw_key_os<K>(sq, ck, x0 + (u32)idx) : (K)0;
+        }
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+            if ((int)threadIdx.x + k * NTHREADS < n) atomicAdd(&s_h[(u32)key[k] & (RADIX - 1)], 1u);
+        __syncthreads();
+        C.pcnt[p * RADIX + threadIdx.x] = s_h[threadIdx.x];
+        __syncthreads();
     }
 }
 
@@ -407,8 +411,8 @@ __global__ __launch_bounds__(NTHREADS) void k_hist_raw(Ctx C) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
     __shared__ i64 s_scan[NTHREADS / 64];
-    __shared__ i64 s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
+    __shared__ i64 s_carry, s_ccarry;
+    if (threadIdx.x == 0) s_carry = s_ccarry = 0;
     __syncthreads();
     for (int b = 0; b < C.nseg; b += NTHREADS) {
         const int q = b + threadIdx.x;
@@ -425,15 +429,96 @@ __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
         }
         i64 tot;
         i64 off = block_excl_scan<i64>(np, s_scan, tot);
+        i64 ctot;
+        const i64 coff = block_excl_scan<i64>((np + SCAN_CH - 1) / SCAN_CH, s_scan, ctot);
         if (q < C.nseg) {
             C.dyn[q].part_first = s_carry + off;
             C.ppre[q] = s_carry + off;
+            C.chpre[q] = s_ccarry + coff;
         }
         __syncthreads();
-        if (threadIdx.x == 0) s_carry += tot;
+        if (threadIdx.x == 0) {
+            s_carry += tot;
+            s_ccarry += ctot;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) C.ppre[C.nseg] = s_carry;
+    if (threadIdx.x == 0) {
+        C.ppre[C.nseg] = s_carry;
+        C.chpre[C.nseg] = s_ccarry;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Partition offsets without look-back: pcnt[p][d] holds partition p's count of
+// digit d (written by a counting kernel); three small kernels turn it into
+// the product-wide position of the partition's first item with that digit.
+//   l1: per chunk of SCAN_CH partitions, the chunk's digit totals;
+//   l2: per product, exclusive prefix over its chunks, and the digit bases
+//       (stage_base + keys of the product with a smaller digit);
+//   l3: per chunk, base + chunk offset + exclusive prefix over its partitions.
+// ---------------------------------------------------------------------------
+__device__ inline void chunk_range(const Ctx &C, i64 ch, int &q, i64 &p0, i64 &p1) {
+    q = seg_search(C.chpre, C.nseg, ch);
+    const i64 c = ch - C.chpre[q];
+    p0 = C.ppre[q] + c * SCAN_CH;
+    p1 = min(C.ppre[q + 1], p0 + SCAN_CH);
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_scan_l1(Ctx C) {
+    const int d = threadIdx.x;  // RADIX == NTHREADS
+    for (i64 ch = blockIdx.x; ch < C.chpre[C.nseg]; ch += gridDim.x) {
+        int q;
+        i64 p0, p1;
+        chunk_range(C, ch, q, p0, p1);
+        u64 v[SCAN_CH];
+#pragma unroll
+        for (int k = 0; k < SCAN_CH; k++) v[k] = p0 + k < p1 ? C.pcnt[(p0 + k) * RADIX + d] : 0;
+        u64 t = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_CH; k++) t += v[k];
+        C.ctot[ch * RADIX + d] = t;
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_scan_l2(Ctx C) {
+    __shared__ u64 s_scan[NTHREADS / 64];
+    const int d = threadIdx.x;
+    for (int q = blockIdx.x; q < C.nseg; q += gridDim.x) {
+        const i64 c0 = C.chpre[q], c1 = C.chpre[q + 1];
+        u64 run = 0;
+        for (i64 cb = c0; cb < c1; cb += SCAN_CH) {
+            // a batch of chunk totals in flight together, then scanned in registers
+            u64 v[SCAN_CH];
+#pragma unroll
+            for (int k = 0; k < SCAN_CH; k++) v[k] = cb + k < c1 ? C.ctot[(cb + k) * RADIX + d] : 0;
+#pragma unroll
+            for (int k = 0; k < SCAN_CH; k++) {
+                if (cb + k < c1) C.ctot[(cb + k) * RADIX + d] = run;
+                run += v[k];
+            }
+        }
+        u64 all;
+        C.pbase[(i64)q * RADIX + d] = (u64)C.segs[q].stage_base + block_excl_scan<u64>(run, s_scan, all);
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_scan_l3(Ctx C) {
+    const int d = threadIdx.x;
+    for (i64 ch = blockIdx.x; ch < C.chpre[C.nseg]; ch += gridDim.x) {
+        int q;
+        i64 p0, p1;
+        chunk_range(C, ch, q, p0, p1);
+        u64 run = C.ctot[ch * RADIX + d] + C.pbase[(i64)q * RADIX + d];
+        u64 v[SCAN_CH];
+#pragma unroll
+        for (int k = 0; k < SCAN_CH; k++) v[k] = p0 + k < p1 ? C.pcnt[(p0 + k) * RADIX + d] : 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_CH; k++) {
+            if (p0 + k < p1) C.pcnt[(p0 + k) * RADIX + d] = run;
+            run += v[k];
+        }
+    }
 }
 
 // Digit offsets of product q for one pass: s_base[d] = stage_base + number of
@@ -482,7 +567,7 @@ struct OsSmem {
 // last in the last digit, i.e. at sorted positions [n, PART), so the valid
 // items' positions are unaffected; only that digit's published count and the
 // global writes account for them.
-template <typename K, typename V, bool GEN>
+template <typename K, typename V, bool GEN, bool PRE>
 __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, i64 p, i64 first,
                                              i64 c, i64 lo, i64 span, int n, const K *__restrict__ kin,
                                              const V *__restrict__ vin, K *__restrict__ kout, V *__restrict__ vout,
@@ -553,7 +638,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     u32 all;
     const u32 loff = block_excl_scan<u32>(tot, S.scan, all);
     if (d == RADIX - 1) tot -= (u32)(PART - n);
-    lb_publish(C.look + p * RADIX + d, first, p, tag, tot);
+    if constexpr (!PRE) lb_publish(C.look + p * RADIX + d, first, p, tag, tot);
     S.loff[d] = loff;
     __syncthreads();
     // keys into LDS in sorted order
@@ -565,9 +650,14 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         S.buf.k[pos] = key[k];
         S.dig[pos] = (unsigned char)dk;
     }
-    // product-wide offset of this digit in this partition
-    const u64 prefix = lookback_batched_resolve(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
-    S.goff[d] = (i64)(S.base[d] + prefix) - (i64)loff;
+    // product-wide offset of this digit in this partition: precomputed, or
+    // the digit base plus a look-back over the product's earlier partitions
+    if constexpr (PRE) {
+        S.goff[d] = (i64)C.pcnt[p * RADIX + d] - (i64)loff;
+    } else {
+        const u64 prefix = lookback_batched_resolve(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
+        S.goff[d] = (i64)(S.base[d] + prefix) - (i64)loff;
+    }
     u32 tk = 0;
     if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition, claimed while this one scatters
     __syncthreads();
@@ -599,7 +689,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     __syncthreads();
 }
 
-template <typename K, typename V, bool GEN>
+template <typename K, typename V, bool GEN, bool PRE>
 __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
@@ -622,15 +712,15 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
         if (q != cur_q) {
             __syncthreads();
             if (cur_q >= 0 && next_hist) hist_flush(C, S.nh, pass + 1, cur_q);
-            seg_digit_bases(C, pass, q, S.base, S.scan64);
+            if constexpr (!PRE) seg_digit_bases(C, pass, q, S.base, S.scan64);
             sq = load_os_seg(C, q);
             cur_q = q;
         }
         __syncthreads();
         const i64 c = p - sq.first;
         const int n = (int)min((i64)PART, sq.n_q - c * PART);
-        os_partition<K, V, GEN>(C, S, sq, pass, p, sq.first, c, sq.lo, sq.n_q, n, kin, vin, kout, vout, next_hist,
-                                ticket);
+        os_partition<K, V, GEN, PRE>(C, S, sq, pass, p, sq.first, c, sq.lo, sq.n_q, n, kin, vin, kout, vout, next_hist,
+                                     ticket);
         p = S.pn;
     }
     if (cur_q >= 0 && next_hist) {
@@ -1195,14 +1285,21 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
             ProfScope ps("hist_raw", st);
             hipLaunchKernelGGL((k_hist_raw<K>), dim3(grid_for(P.nparts_bound, cus * 8)), dim3(NTHREADS), 0, st, C);
         }
+        {
+            ProfScope ps("part_scan", st);
+            const int gc = grid_for(P.nparts_bound / SCAN_CH + P.nseg + 1, cus * 4);
+            hipLaunchKernelGGL(k_scan_l1, dim3(gc), dim3(NTHREADS), 0, st, C);
+            hipLaunchKernelGGL(k_scan_l2, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C);
+            hipLaunchKernelGGL(k_scan_l3, dim3(gc), dim3(NTHREADS), 0, st, C);
+        }
         ProfScope ps("onesweep_gen", st);
-        hipLaunchKernelGGL((k_onesweep<K, V, true>), dim3(g), dim3(NTHREADS), 0, st, C, 0, ka, va, kb, vb);
+        hipLaunchKernelGGL((k_onesweep<K, V, true, true>), dim3(g), dim3(NTHREADS), 0, st, C, 0, ka, va, kb, vb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
     for (int pass = (P.raw ? 1 : 0); pass < P.passes; pass++) {
         ProfScope ps("onesweep", st);
-        hipLaunchKernelGGL((k_onesweep<K, V, false>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
+        hipLaunchKernelGGL((k_onesweep<K, V, false, false>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
@@ -1303,6 +1400,10 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.box = (u64 *)(b + P.o_box);
     C.hist = (unsigned long long *)(b + P.o_hist);
     C.look = (u64 *)(b + P.o_look);
+    C.pcnt = (u64 *)(b + P.o_pcnt);
+    C.ctot = (u64 *)(b + P.o_ctot);
+    C.chpre = (i64 *)(b + P.o_chpre);
+    C.pbase = (u64 *)(b + P.o_pbase);
     C.look_red = (u64 *)(b + P.o_look_red);
     C.look_cmp = (u64 *)(b + P.o_look_cmp);
     C.look_tile = (u64 *)(b + P.o_look_tile);

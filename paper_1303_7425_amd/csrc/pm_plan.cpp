@@ -320,6 +320,10 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.r_zero.off = zero0;
     P.r_zero.bytes = off - zero0;
     P.o_ppre = take((size_t)8 * (S + 1));
+    P.o_chpre = take((size_t)8 * (S + 1));
+    P.o_pbase = take((size_t)8 * RADIX * S);
+    P.o_pcnt = take((size_t)8 * RADIX * std::max<int64_t>(1, P.nparts_bound));
+    P.o_ctot = take((size_t)8 * RADIX * (P.nparts_bound / SCAN_CH + S + 1));
     P.o_iv_samp = take((size_t)P.ksize * std::max<int64_t>(1, P.iv_nsamp));
     P.o_iv_spl = take((size_t)P.ksize * std::max<int64_t>(1, P.iv_nspl));
     P.o_iv_cur = take((size_t)4 * std::max<int64_t>(1, (int64_t)P.iv_grid * P.iv_maxrows));
