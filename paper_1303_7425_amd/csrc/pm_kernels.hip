@@ -375,7 +375,7 @@ __device__ inline K raw_key_os(const OsSeg &s, const K *ck, u32 x) {
 
 template <typename K>
 __global__ __launch_bounds__(NTHREADS) void k_hist_raw(Ctx C) {
-    __shared__ u32 s_h[RADIX];
+    __shared__ u32 s_h[RADIX];  // this partition's digit-0 counts
     const i64 nparts = C.ppre[C.nseg];
     const K *ck = (const K *)C.ck;
     int cur_q = -1;
@@ -398,8 +398,9 @@ __global__ __launch_bounds__(NTHREADS) void k_hist_raw(Ctx C) {
             key[k] = idx < n ? raw_key_os<K>(sq, ck, x0 + (u32)idx) : (K)0;
         }
 #pragma unroll
-        for (int k = 0; k < IPT; k++)
+        for (int k = 0; k < IPT; k++) {
             if ((int)threadIdx.x + k * NTHREADS < n) atomicAdd(&s_h[(u32)key[k] & (RADIX - 1)], 1u);
+        }
         __syncthreads();
         C.pcnt[p * RADIX + threadIdx.x] = s_h[threadIdx.x];
         __syncthreads();
@@ -608,16 +609,22 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
             val[k] = idx < n ? vin[start + idx] : (V)0;
         }
     }
-    // per-wave stable ranking
+    // per-wave stable ranking: a lane's peers are the lanes whose digit equals
+    // its own; per digit bit, the ballot of lanes with the bit set XOR this
+    // lane's bit broadcast to all ones or zeros marks the lanes that differ
+    // (every lane of the wave is active here: missing items carry a key)
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
         const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
-        u64 peers = ~0ull;
+        u32 mis_lo = 0, mis_hi = 0;
 #pragma unroll
         for (int b = 0; b < RADIX_BITS; b++) {
-            const u64 m = __ballot((d >> b) & 1);
-            peers &= ((d >> b) & 1) ? m : ~m;
+            const u32 t = (u32)((i32)(d << (31 - b)) >> 31);
+            const u64 m = __ballot(t != 0);
+            mis_lo |= (u32)m ^ t;
+            mis_hi |= (u32)(m >> 32) ^ t;
         }
+        const u64 peers = ~(((u64)mis_hi << 32) | mis_lo);
         const u32 before = mbcnt(peers);
         const u32 old = S.wh[w][d];
         if (before == 0) S.wh[w][d] = old + (u32)__popcll(peers);
