@@ -272,7 +272,7 @@ __device__ inline T wave_incl_scan(T x) {
 
 // Exclusive scan over the 256 threads of a workgroup.  `scratch` holds 4 T.
 // Contains two barriers; every thread must call it.
-template <typename T>
+template <typename T, int NT = NTHREADS>
 __device__ inline T block_excl_scan(T v, T *scratch, T &total) {
     const u32 lane = lane_id();
     const u32 w = threadIdx.x >> 6;
@@ -281,7 +281,7 @@ __device__ inline T block_excl_scan(T v, T *scratch, T &total) {
     __syncthreads();
     T pre = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < NTHREADS / 64; i++) {
+    for (int i = 0; i < NT / 64; i++) {
         T s = scratch[i];
         if ((u32)i < w) pre += s;
         tot += s;

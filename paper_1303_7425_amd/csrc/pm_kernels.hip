@@ -813,13 +813,17 @@ __device__ inline u64 item_value_rd(const RdSeg &s, V v) {
 }
 
 constexpr u32 TAG_REDUCE = 200u, TAG_ZCOMPACT = 201u;
+// The reduction runs 512-thread workgroups with 8 items per thread (one
+// partition of PART items): the same LDS per workgroup as 256 x 16, twice the
+// waves per CU to hide its load, gather and look-back latencies.
+constexpr int RED_T = 512, RED_IPT = PART / RED_T;
 
 template <typename K, typename V, int RING>
-__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_reduce(Ctx C, const K *__restrict__ kin, const V *__restrict__ vin) {
+__global__ __launch_bounds__(RED_T) void k_reduce(Ctx C, const K *__restrict__ kin, const V *__restrict__ vin) {
     constexpr int PADN = PART + PART / 16;
     __shared__ K s_k[PADN];
     __shared__ u64 s_v[PADN];
-    __shared__ u32 s_scan[NTHREADS / 64];
+    __shared__ u32 s_scan[RED_T / 64];
     __shared__ i64 s_p, s_pn;
     __shared__ u64 s_base;
     __shared__ u32 s_z;
@@ -847,29 +851,29 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
         int tid = (int)threadIdx.x;
         asm volatile("" : "+v"(tid));
         // keys and raw payloads, register-blocked and coalesced
-        K kr[IPT];
-        V vr[IPT];
+        K kr[RED_IPT];
+        V vr[RED_IPT];
 #pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int i = tid + r * NTHREADS;
+        for (int r = 0; r < RED_IPT; r++) {
+            const int i = tid + r * RED_T;
             kr[r] = i < n ? kin[start + i] : (K)0;
             vr[r] = i < n ? vin[start + i] : (V)0;
         }
 #pragma unroll
-        for (int r = 0; r < IPT; r++) {
-            const int i = tid + r * NTHREADS;
+        for (int r = 0; r < RED_IPT; r++) {
+            const int i = tid + r * RED_T;
             if (i < n) s_k[pad(i)] = kr[r];
         }
         const K prevk = c > 0 ? kin[start - 1] : (K)0;
         __syncthreads();
-        // run heads among this thread's items [b0, b0 + IPT); publish the count
-        const int b0 = tid * IPT;
+        // run heads among this thread's items [b0, b0 + RED_IPT); publish the count
+        const int b0 = tid * RED_IPT;
         u32 hm = 0;
         {
             K kp = b0 == 0 ? prevk : s_k[pad(b0 > 0 ? b0 - 1 : 0)];
             bool hp = !(b0 == 0 && c == 0);
 #pragma unroll
-            for (int r = 0; r < IPT; r++) {
+            for (int r = 0; r < RED_IPT; r++) {
                 if (b0 + r < n) {
                     const K key = s_k[pad(b0 + r)];
                     if (!hp || key != kp) hm |= 1u << r;
@@ -879,30 +883,30 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
             }
         }
         u32 total;
-        const u32 off = block_excl_scan<u32>((u32)__popc(hm), s_scan, total);
+        const u32 off = block_excl_scan<u32, RED_T>((u32)__popc(hm), s_scan, total);
         if (threadIdx.x == 0) lb_publish(C.look_red + p, first, p, TAG_REDUCE, total);
         // item values: the operand gathers of all of a thread's items in flight together
         {
-            u64 xv[IPT];
+            u64 xv[RED_IPT];
             if constexpr (sizeof(V) == 8) {
 #pragma unroll
-                for (int r = 0; r < IPT; r++) xv[r] = (u64)vr[r];
+                for (int r = 0; r < RED_IPT; r++) xv[r] = (u64)vr[r];
             } else {
-                u64 fa[IPT], gb[IPT];
+                u64 fa[RED_IPT], gb[RED_IPT];
 #pragma unroll
-                for (int r = 0; r < IPT; r++) {
-                    const int i = tid + r * NTHREADS;
+                for (int r = 0; r < RED_IPT; r++) {
+                    const int i = tid + r * RED_T;
                     const u32 a = i < n ? div32((u32)vr[r], s.nb_div) : 0u;
                     const u32 b = i < n ? (u32)vr[r] - a * (u32)s.nb : 0u;
                     fa[r] = s.fc[a];
                     gb[r] = s.gc[b];
                 }
 #pragma unroll
-                for (int r = 0; r < IPT; r++) xv[r] = ring_mul<RING>(fa[r], gb[r]);
+                for (int r = 0; r < RED_IPT; r++) xv[r] = ring_mul<RING>(fa[r], gb[r]);
             }
 #pragma unroll
-            for (int r = 0; r < IPT; r++) {
-                const int i = tid + r * NTHREADS;
+            for (int r = 0; r < RED_IPT; r++) {
+                const int i = tid + r * RED_T;
                 if (i < n) s_v[pad(i)] = xv[r];
             }
         }
@@ -912,7 +916,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
             int open = -1;
             u64 acc = 0;
 #pragma unroll
-            for (int r = 0; r < IPT; r++) {
+            for (int r = 0; r < RED_IPT; r++) {
                 if (b0 + r < n) {
                     const u64 v = s_v[pad(b0 + r)];
                     if ((hm >> r) & 1) {
@@ -927,7 +931,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
             if (open >= 0) {
                 // the last run may continue into the next threads' items and partitions
                 const K key = s_k[pad(b0 + open)];
-                int j = b0 + IPT;
+                int j = b0 + RED_IPT;
                 while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
                 if (j >= n && n > 0) {
                     for (i64 g = start + n; g < send && kin[g] == key; g++)
@@ -944,17 +948,17 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
         u32 tk = 0;
         if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition
         // gather this thread's runs, then stage them by slot in LDS
-        K ok[IPT];
-        u64 ov[IPT];
+        K ok[RED_IPT];
+        u64 ov[RED_IPT];
 #pragma unroll
-        for (int r = 0; r < IPT; r++) {
+        for (int r = 0; r < RED_IPT; r++) {
             ok[r] = s_k[pad(b0 + r)];
             ov[r] = s_v[pad(b0 + r)];
         }
         __syncthreads();
         u32 o = off, zc = 0;
 #pragma unroll
-        for (int r = 0; r < IPT; r++) {
+        for (int r = 0; r < RED_IPT; r++) {
             if ((hm >> r) & 1) {
                 s_k[o] = ok[r];
                 s_v[o] = ov[r];
@@ -966,7 +970,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
         __syncthreads();
         const u64 base = s_base;
         const VarParam *vp = C.vars + s.var_off;
-        for (int i = threadIdx.x; i < (int)total; i += NTHREADS) {
+        for (int i = threadIdx.x; i < (int)total; i += RED_T) {
             const u64 pos = base + i;
             if ((i64)pos < s.cap) {
                 s.hk[pos] = decompress<K>(s_k[i], vp, C.nvars, s.lo_key);
@@ -1312,7 +1316,7 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
     }
     {
         ProfScope ps("reduce", st);
-        hipLaunchKernelGGL((k_reduce<K, V, RING>), dim3(grid_for(P.nparts_bound, cus * 3)), dim3(NTHREADS), 0, st, C,
+        hipLaunchKernelGGL((k_reduce<K, V, RING>), dim3(grid_for(P.nparts_bound, cus * 3)), dim3(RED_T), 0, st, C,
                            ka, va);
     }
     ProfScope ps("zero_compact", st);
