@@ -737,14 +737,74 @@ __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K 
 }
 
 // ---------------------------------------------------------------------------
+// Result slots without look-back.  k_head_count: the number of runs (distinct
+// keys) that start in each reduce partition of the sorted staging, into
+// pcnt[p]; k_head_scan: per product, the exclusive prefix over its partitions,
+// i.e. the slot of each partition's first run.
+// ---------------------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(NTHREADS) void k_head_count(Ctx C, const K *__restrict__ kin) {
+    __shared__ u32 s_scan[NTHREADS / 64];
+    const i64 nparts = C.ppre[C.nseg];
+    int cur_q = -1;
+    OsSeg sq{};
+    for (i64 p = blockIdx.x; p < nparts; p += gridDim.x) {
+        const int q = (cur_q >= 0 && p < sq.first + (sq.n_q + PART - 1) / PART) ? cur_q : seg_search(C.ppre, C.nseg, p);
+        if (q != cur_q) {
+            sq = load_os_seg(C, q);
+            cur_q = q;
+        }
+        const i64 c = p - sq.first;
+        const i64 start = sq.lo + c * PART;
+        const int n = (int)min((i64)PART, sq.n_q - c * PART);
+        K key[IPT], prev[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int i = (int)threadIdx.x + r * NTHREADS;
+            key[r] = i < n ? kin[start + i] : (K)0;
+            prev[r] = (i < n && (i > 0 || c > 0)) ? kin[start + i - 1] : (K)0;
+        }
+        u32 h = 0;
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const int i = (int)threadIdx.x + r * NTHREADS;
+            if (i < n && ((i == 0 && c == 0) || key[r] != prev[r])) h++;
+        }
+        u32 tot;
+        (void)block_excl_scan<u32>(h, s_scan, tot);
+        if (threadIdx.x == 0) C.pcnt[p] = tot;
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_head_scan(Ctx C) {
+    __shared__ u64 s_scan[NTHREADS / 64];
+    for (int q = blockIdx.x; q < C.nseg; q += gridDim.x) {
+        const i64 p0 = C.ppre[q], np = C.ppre[q + 1] - p0;
+        const i64 B = (np + NTHREADS - 1) / NTHREADS;  // partitions per thread, blocked
+        const i64 b0 = p0 + (i64)threadIdx.x * B, b1 = min(p0 + np, b0 + B);
+        u64 t = 0;
+#pragma unroll 8
+        for (i64 p = b0; p < b1; p++) t += C.pcnt[p];
+        u64 all;
+        u64 run = block_excl_scan<u64>(t, s_scan, all);
+#pragma unroll 8
+        for (i64 p = b0; p < b1; p++) {
+            const u64 v = C.pcnt[p];
+            C.pcnt[p] = run;
+            run += v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_reduce: sorted staging -> result.  A run of equal keys is summed by the
 // thread that owns its first element, left to right in staging order (for
 // FP64 that is the row-major (i, j) order of the pp-matrix, as the sort is
 // stable and SEG_RAW items start in index order), continuing past the
 // thread's items and the partition end when the run does.  Every run gets
 // the result slot given by its rank among the product's runs, which is known
-// from the keys alone: the partition publishes its run count before it
-// gathers the operands, and resolves its offset after summing.  A run whose
+// from the keys alone: the partition's first slot comes from k_head_count and
+// k_head_scan.  A run whose
 // sum cancels to zero leaves a slot with a zero coefficient; k_zero_compact
 // removes those slots afterwards (only products that have any).  Results are
 // staged in LDS and written out contiguously with the key decompressed to the
@@ -812,7 +872,7 @@ __device__ inline u64 item_value_rd(const RdSeg &s, V v) {
     }
 }
 
-constexpr u32 TAG_REDUCE = 200u, TAG_ZCOMPACT = 201u;
+constexpr u32 TAG_ZCOMPACT = 201u;
 // The reduction runs 512-thread workgroups with 8 items per thread (one
 // partition of PART items): the same LDS per workgroup as 256 x 16, twice the
 // waves per CU to hide its load, gather and look-back latencies.
@@ -884,7 +944,7 @@ __global__ __launch_bounds__(RED_T) void k_reduce(Ctx C, const K *__restrict__ k
         }
         u32 total;
         const u32 off = block_excl_scan<u32, RED_T>((u32)__popc(hm), s_scan, total);
-        if (threadIdx.x == 0) lb_publish(C.look_red + p, first, p, TAG_REDUCE, total);
+        if (threadIdx.x == 0) s_base = C.pcnt[p];
         // item values: the operand gathers of all of a thread's items in flight together
         {
             u64 xv[RED_IPT];
@@ -939,11 +999,6 @@ __global__ __launch_bounds__(RED_T) void k_reduce(Ctx C, const K *__restrict__ k
                 }
                 s_v[pad(b0 + open)] = acc;
             }
-        }
-        // product-wide slot of this partition's first run
-        if (threadIdx.x < 64) {
-            const u64 pre = lookback_wave_resolve(C.look_red, first, p, TAG_REDUCE, total, &C.counters[CNT_ERR_SPIN]);
-            if (threadIdx.x == 0) s_base = pre;
         }
         u32 tk = 0;
         if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition
@@ -1313,6 +1368,11 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         hipLaunchKernelGGL((k_onesweep<K, V, false, false>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
         std::swap(ka, kb);
         std::swap(va, vb);
+    }
+    {
+        ProfScope ps("head_count", st);
+        hipLaunchKernelGGL((k_head_count<K>), dim3(grid_for(P.nparts_bound, cus * 8)), dim3(NTHREADS), 0, st, C, ka);
+        hipLaunchKernelGGL(k_head_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C);
     }
     {
         ProfScope ps("reduce", st);
