@@ -299,43 +299,18 @@ __device__ inline u64 lb_load(u64 *p) { return __hip_atomic_load(p, __ATOMIC_REL
 
 constexpr u32 LB_SPIN_LIMIT = 1u << 24;
 
-// Decoupled look-back: exclusive prefix of `value` over partitions
-// [first, p) that published under `tag`.  Partition p publishes its own
-// aggregate first, then its inclusive prefix.  Work-queue order guarantees
-// that every earlier partition belongs to a running or finished workgroup.
-__device__ inline u64 lookback(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
-    if (p == first) {
-        lb_store(look + p * stride, lb_pack(tag, LB_INC, value));
-        return 0;
-    }
-    lb_store(look + p * stride, lb_pack(tag, LB_AGG, value));
-    u64 prefix = 0;
-    i64 j = p - 1;
-    u32 spins = 0;
-    while (true) {
-        u64 v = lb_load(look + j * stride);
-        if ((u32)(v >> 56) != tag) {
-            if (++spins > LB_SPIN_LIMIT) {
-                atomicOr(err, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        prefix += v & ((1ull << 54) - 1);
-        if (((v >> 54) & 3) == LB_INC || j == first) break;
-        j--;
-    }
-    lb_store(look + p * stride, lb_pack(tag, LB_INC, prefix + value));
-    return prefix;
-}
-
 __device__ inline u64 wave_sum_u64(u64 v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
 }
 
+// Decoupled look-back: partition p publishes its own aggregate, later its
+// inclusive prefix; a successor sums the words of its predecessors back to the
+// nearest inclusive prefix.  Partitions are taken from a work queue in order,
+// so every earlier partition belongs to a running or finished workgroup and
+// each wait ends (a bounded spin flags an error instead of hanging).
+//
 // Publishes partition p's own aggregate: its inclusive prefix when p is the
 // product's first partition.  Publishing early, and resolving the prefix
 // later, gives the predecessors time to publish theirs.
@@ -382,10 +357,6 @@ __device__ inline u64 lookback_batched_resolve(u64 *look, i64 stride, i64 first,
     return prefix;
 }
 
-__device__ inline u64 lookback_batched(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value, u32 *err) {
-    lb_publish(look + p * stride, first, p, tag, value);
-    return lookback_batched_resolve(look, stride, first, p, tag, value, err);
-}
 
 // Wave-cooperative decoupled look-back for one counter per partition.  All
 // 64 lanes of one wave call it with the same (first, p); lane l inspects

@@ -326,12 +326,6 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
 // on the fly; the partition-offset scan turns them into the generating pass's
 // scatter offsets, so that pass needs no look-back.
 // ---------------------------------------------------------------------------
-template <typename K>
-__device__ inline K raw_key(const DevSeg &s, const K *ck, u32 x) {
-    const u32 i = div32(x, s.nb_div);
-    const u32 j = x - i * (u32)s.nb;
-    return ck[s.ck_f + i] + ck[s.ck_g + j];
-}
 
 // Wave-uniform value held in scalar registers.
 __device__ inline i64 uniform64(i64 v) {
@@ -810,16 +804,6 @@ __global__ __launch_bounds__(NTHREADS) void k_head_scan(Ctx C) {
 // staged in LDS and written out contiguously with the key decompressed to the
 // packed exponent layout.
 // ---------------------------------------------------------------------------
-template <typename K, typename V, int RING>
-__device__ inline u64 item_value(const DevSeg &s, V v) {
-    if constexpr (sizeof(V) == 8) {
-        return (u64)v;
-    } else {
-        const u32 i = div32((u32)v, s.nb_div);
-        const u32 j = (u32)v - i * (u32)s.nb;
-        return ring_mul<RING>(s.fc[i], s.gc[j]);
-    }
-}
 
 // The fields of one product that the reduction uses, kept in scalar
 // registers while consecutive partitions belong to the same product.
