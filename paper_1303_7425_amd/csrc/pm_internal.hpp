@@ -30,7 +30,7 @@ constexpr int IV_SAMPLES_MAX = 4096;   // grid samples per product ((l+1)^2, l <
 constexpr int NTHREADS = 256;          // threads per workgroup (4 wave64s)
 constexpr int IPT = 16;                // items per thread in sort / reduce partitions
 constexpr int PART = NTHREADS * IPT;   // items per partition
-constexpr int SCAN_CH = 32;            // partitions per chunk of the partition-offset scan
+constexpr int RNG = 64;                // sort blocks per range
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
@@ -124,12 +124,12 @@ struct Ctx {
     void *stA_k, *stA_v;
     void *stB_k, *stB_v;
     u64 *box;
-    unsigned long long *hist;   // [passes][nseg][RADIX] digit counts per product
-    u64 *look;                  // sort lookback [nparts_bound][RADIX]
-    u64 *pcnt;                  // per-partition digit counts, then offsets [nparts_bound][RADIX]
-    u64 *ctot;                  // per-chunk digit totals, then offsets [nchunks][RADIX]
-    i64 *chpre;                 // [nseg+1] chunk prefix over products (device computed)
-    u64 *pbase;                 // [nseg][RADIX] digit bases of the partition-offset scan
+    u64 *pcnt;                  // per-partition run-head counts, then first result slots [nparts_bound]
+    u64 *ctot;                  // digit counts of the current radix pass per sort block [nblocks][RADIX]
+    u64 *rtot;                  // the same per range of RNG blocks [2][nrng][RADIX], by pass parity
+    i64 nrng;                   // range rows per parity
+    i64 *chpre;                 // [nseg+1] sort-block prefix over products (device computed)
+    i64 *rpre;                  // [nseg+1] range prefix over products (device computed)
     u64 *look_red;              // reduce lookback [nparts_bound]
     u64 *look_cmp;              // dense compaction lookback [ndparts]
     u64 *look_tile;             // staging offsets of combined tiles [ntiles]
@@ -145,6 +145,7 @@ struct Ctx {
     i64 iv_items;
     i32 nseg, ntseg, ndseg;
     i32 nvars, bits, passes, ring;
+    i64 pblk;                   // sort partitions per sort block
     i64 ntiles, ndparts;
     i32 raw;                    // sparse products carry pair indices (SEG_RAW) instead of values
     i32 tb_tile, tb_sort, tb_cmp;  // consecutive work items handed out per work-queue ticket
@@ -317,46 +318,6 @@ __device__ inline u64 wave_sum_u64(u64 v) {
 __device__ inline void lb_publish(u64 *slot, i64 first, i64 p, u32 tag, u64 value) {
     lb_store(slot, lb_pack(tag, p == first ? LB_INC : LB_AGG, value));
 }
-
-// Per-thread decoupled look-back over a strided counter array (one counter
-// per digit), reading up to four predecessors per round trip.  The partition
-// has already published its aggregate with lb_publish.
-__device__ inline u64 lookback_batched_resolve(u64 *look, i64 stride, i64 first, i64 p, u32 tag, u64 value,
-                                               u32 *err) {
-    if (p == first) return 0;
-    u64 prefix = 0;
-    i64 j = p - 1;
-    u32 spins = 0;
-    while (true) {
-        u64 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++) v[k] = (j - k >= first) ? lb_load(look + (j - k) * stride) : 0;
-        bool done = false;
-        int used = 0;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            if (done || used < k) break;
-            if (j - k < first) {
-                done = true;
-                break;
-            }
-            if ((u32)(v[k] >> 56) != tag) break;
-            prefix += v[k] & ((1ull << 54) - 1);
-            used++;
-            if (((v[k] >> 54) & 3) == LB_INC) done = true;
-        }
-        if (done) break;
-        j -= used;
-        if (j < first) break;
-        if (used == 0 && ++spins > LB_SPIN_LIMIT) {
-            atomicOr(err, 1u);
-            break;
-        }
-    }
-    lb_store(look + p * stride, lb_pack(tag, LB_INC, prefix + value));
-    return prefix;
-}
-
 
 // Wave-cooperative decoupled look-back for one counter per partition.  All
 // 64 lanes of one wave call it with the same (first, p); lane l inspects

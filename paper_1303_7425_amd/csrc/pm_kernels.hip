@@ -6,11 +6,14 @@
 //   k_tile       f-block x g-block tile of term products expanded into LDS and
 //                combined there with an LDS hash (exact rings); unique pairs go
 //                to a staging buffer (sparse) or into the degree-box array (dense)
-//   k_hist_raw   digit histogram of products sorted by pair index (SEG_RAW)
-//   k_seg_prepare per-product sizes and sort partitions
-//   k_onesweep   one stable LSD radix pass (8-bit digit) with decoupled look-back;
+//   k_seg_prepare per-product sizes, sort partitions, sort blocks
+//   k_count      digit counts per sort block before each radix pass
+//   k_onesweep   one stable LSD radix pass (8-bit digit); a workgroup ranks one
+//                sort block's partitions in order from precomputed positions;
 //                pass 0 of SEG_RAW generates its keys from the operands
-//   k_reduce     segmented like-term reduction + zero drop + key decompression
+//   k_head_count run heads per reduce partition, k_head_scan their prefix
+//   k_reduce     segmented like-term reduction + key decompression
+//   k_zero_compact removal of runs that cancelled to zero
 //   k_compact    dense path: degree-box cells -> sorted non-zero terms
 //
 // The schoolbook product P = sum_{i,j} a_i b_j x^{alpha_i + beta_j} and the
@@ -113,8 +116,9 @@ __global__ __launch_bounds__(NTHREADS) void k_stats(const DevSeg *segs, int nvar
 }
 
 // ---------------------------------------------------------------------------
-// Fill a u64 region (the per-call zeroed state: counters, histograms,
-// look-back words, dense box).  A kernel, so that graph replays stay valid.
+// Fill a u64 region (the per-call zeroed state: counters, range counters of
+// the radix passes, look-back words, dense box).  A kernel, so that graph
+// replays stay valid.
 // ---------------------------------------------------------------------------
 __global__ void k_fill(u64 *p, i64 n, u64 v) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
@@ -139,21 +143,6 @@ __global__ __launch_bounds__(NTHREADS) void k_compress(Ctx C, const i64 *cpre, i
             ck += (e - (side ? vp[v].ming : vp[v].minf)) * vp[v].stride;
         }
         ((K *)C.ck)[(side ? s.ck_g : s.ck_f) + i] = (K)ck;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Digit histograms.  hist[pass][segment][digit] holds the count of staged
-// keys with that digit; a workgroup accumulates in LDS while it stays on one
-// product and flushes with one global atomic per non-zero bin.
-// ---------------------------------------------------------------------------
-__device__ inline void hist_flush(Ctx &C, u32 *s_h, int pass, int q) {
-    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) {
-        const u32 v = s_h[d];
-        if (v) {
-            atomicAdd(C.hist + ((i64)pass * C.nseg + q) * RADIX + d, (unsigned long long)v);
-            s_h[d] = 0;
-        }
     }
 }
 
@@ -196,14 +185,11 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
     __shared__ u64 s_fc[TM], s_gc[TN];
     __shared__ K s_hk[HS + HS / 16];   // padded: slot h lives at h + h/16
     __shared__ u64 s_hv[HS + HS / 16];
-    __shared__ u32 s_h0[RADIX];
     __shared__ u32 s_scan[NTHREADS / 64];
     __shared__ i64 s_tile;
     __shared__ u64 s_base;
     auto pad = [](int h) { return h + (h >> 4); };
 
-    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) s_h0[d] = 0;
-    int cur_q = -1;
     const i64 tb = C.tb_tile;
     while (true) {
         if (threadIdx.x == 0) s_tile = (i64)atomicAdd(&C.counters[CNT_TILE], 1u) * tb;
@@ -219,10 +205,6 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
         const i64 i0 = (local / s.tiles_n) * TM, j0 = (local % s.tiles_n) * TN;
         const int tm = (int)min((i64)TM, s.na - i0), tn = (int)min((i64)TN, s.nb - j0);
         const bool dense = s.mode == SEG_DENSE;
-        if (!dense && q != cur_q) {
-            if (cur_q >= 0 && C.passes > 0) hist_flush(C, s_h0, 0, cur_q);
-            cur_q = q;
-        }
         const K *ck = (const K *)C.ck;
         for (int e = threadIdx.x; e < TM; e += NTHREADS)
             if (e < tm) {
@@ -306,27 +288,18 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
                 if (ring_is_zero<RING>(v)) continue;
                 sk[base + w] = s_hk[h];
                 sv[base + w] = v;
-                if (C.passes > 0) atomicAdd(&s_h0[(u32)s_hk[h] & (RADIX - 1)], 1u);
                 w++;
             }
         }
         __syncthreads();
         }
     }
-    if (cur_q >= 0 && C.passes > 0) {
-        __syncthreads();
-        hist_flush(C, s_h0, 0, cur_q);
-    }
 }
 
 // ---------------------------------------------------------------------------
 // SEG_RAW products: pair (i, j) of the pp-matrix has index x = i*nb + j; the
 // sort carries (key, x) and the reduction regenerates a_i * b_j from x.
-// k_hist_raw: digit-0 counts of every sort partition (pcnt), keys generated
-// on the fly; the partition-offset scan turns them into the generating pass's
-// scatter offsets, so that pass needs no look-back.
 // ---------------------------------------------------------------------------
-
 // Wave-uniform value held in scalar registers.
 __device__ inline i64 uniform64(i64 v) {
     const u32 lo = __builtin_amdgcn_readfirstlane((u32)(u64)v);
@@ -367,47 +340,13 @@ __device__ inline K raw_key_os(const OsSeg &s, const K *ck, u32 x) {
     return ck[s.ck_f + i] + ck[s.ck_g + j];
 }
 
-template <typename K>
-__global__ __launch_bounds__(NTHREADS) void k_hist_raw(Ctx C) {
-    __shared__ u32 s_h[RADIX];  // this partition's digit-0 counts
-    const i64 nparts = C.ppre[C.nseg];
-    const K *ck = (const K *)C.ck;
-    int cur_q = -1;
-    OsSeg sq{};
-    for (i64 p = blockIdx.x; p < nparts; p += gridDim.x) {
-        s_h[threadIdx.x] = 0;  // RADIX == NTHREADS
-        const int q = (cur_q >= 0 && p < sq.first + (sq.n_q + PART - 1) / PART) ? cur_q : seg_search(C.ppre, C.nseg, p);
-        if (q != cur_q) {
-            sq = load_os_seg(C, q);
-            cur_q = q;
-        }
-        __syncthreads();
-        const i64 c = p - sq.first;
-        const int n = (int)min((i64)PART, sq.n_q - c * PART);
-        const u32 x0 = (u32)(c * PART);
-        K key[IPT];
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            const int idx = (int)threadIdx.x + k * NTHREADS;
-            key[k] = idx < n ? raw_key_os<K>(sq, ck, x0 + (u32)idx) : (K)0;
-        }
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            if ((int)threadIdx.x + k * NTHREADS < n) atomicAdd(&s_h[(u32)key[k] & (RADIX - 1)], 1u);
-        }
-        __syncthreads();
-        C.pcnt[p * RADIX + threadIdx.x] = s_h[threadIdx.x];
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Per-product sizes and sort partitions (one workgroup).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
     __shared__ i64 s_scan[NTHREADS / 64];
-    __shared__ i64 s_carry, s_ccarry;
-    if (threadIdx.x == 0) s_carry = s_ccarry = 0;
+    __shared__ i64 s_carry, s_ccarry, s_rcarry;
+    if (threadIdx.x == 0) s_carry = s_ccarry = s_rcarry = 0;
     __syncthreads();
     for (int b = 0; b < C.nseg; b += NTHREADS) {
         const int q = b + threadIdx.x;
@@ -425,120 +364,142 @@ __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
         i64 tot;
         i64 off = block_excl_scan<i64>(np, s_scan, tot);
         i64 ctot;
-        const i64 coff = block_excl_scan<i64>((np + SCAN_CH - 1) / SCAN_CH, s_scan, ctot);
+        const i64 nbq = (np + C.pblk - 1) / C.pblk;
+        const i64 coff = block_excl_scan<i64>(nbq, s_scan, ctot);
+        i64 rtot;
+        const i64 roff = block_excl_scan<i64>((nbq + RNG - 1) / RNG, s_scan, rtot);
         if (q < C.nseg) {
             C.dyn[q].part_first = s_carry + off;
             C.ppre[q] = s_carry + off;
             C.chpre[q] = s_ccarry + coff;
+            C.rpre[q] = s_rcarry + roff;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             s_carry += tot;
             s_ccarry += ctot;
+            s_rcarry += rtot;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         C.ppre[C.nseg] = s_carry;
         C.chpre[C.nseg] = s_ccarry;
+        C.rpre[C.nseg] = s_rcarry;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Partition offsets without look-back: pcnt[p][d] holds partition p's count of
-// digit d (written by a counting kernel); three small kernels turn it into
-// the product-wide position of the partition's first item with that digit.
-//   l1: per chunk of SCAN_CH partitions, the chunk's digit totals;
-//   l2: per product, exclusive prefix over its chunks, and the digit bases
-//       (stage_base + keys of the product with a smaller digit);
-//   l3: per chunk, base + chunk offset + exclusive prefix over its partitions.
+// Sort blocks.  Each product's sort partitions are cut into blocks of pblk
+// consecutive partitions (pblk chosen so that the blocks about fill the
+// resident grid), and the blocks into ranges of RNG blocks (chpre / rpre:
+// block and range prefixes over products).  Before every radix pass the
+// counting kernel writes each block's digit histogram (ctot) and adds it into
+// its range's counter (rtot, one set per pass parity).  A radix pass
+// takes one block at a time: its first position per digit is the digit base
+// (keys of the product with a smaller digit) plus the counts of the earlier
+// ranges and of the range's earlier blocks; it then ranks the block's
+// partitions in order and carries the positions itself.  No look-back between
+// workgroups and no work queue.
 // ---------------------------------------------------------------------------
-__device__ inline void chunk_range(const Ctx &C, i64 ch, int &q, i64 &p0, i64 &p1) {
-    q = seg_search(C.chpre, C.nseg, ch);
-    const i64 c = ch - C.chpre[q];
-    p0 = C.ppre[q] + c * SCAN_CH;
-    p1 = min(C.ppre[q + 1], p0 + SCAN_CH);
-}
-
-__global__ __launch_bounds__(NTHREADS) void k_scan_l1(Ctx C) {
-    const int d = threadIdx.x;  // RADIX == NTHREADS
-    for (i64 ch = blockIdx.x; ch < C.chpre[C.nseg]; ch += gridDim.x) {
-        int q;
-        i64 p0, p1;
-        chunk_range(C, ch, q, p0, p1);
-        u64 v[SCAN_CH];
+// Digit counts of one sort block (digit `pass`; GEN: digit 0 of SEG_RAW pair
+// keys generated on the fly), two partitions per step so that their loads are
+// in flight together.  Writes the block's histogram, adds it into its range's
+// counter of this pass's parity, and clears the other parity's row of the
+// range for the next pass (the first block of each range does).
+template <typename K, bool GEN>
+__global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__restrict__ kin) {
+    __shared__ u32 s_h[RADIX];
+    const int shift = pass * RADIX_BITS;
+    u64 *rt = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
+    u64 *rz = C.rtot + (i64)((pass + 1) & 1) * C.nrng * RADIX;
+    const K *ck = (const K *)C.ck;
+    const i64 nblk = C.chpre[C.nseg];
+    int cur_q = -1;
+    OsSeg sq{};
+    for (i64 b = blockIdx.x; b < nblk; b += gridDim.x) {
+        s_h[threadIdx.x] = 0;  // RADIX == NTHREADS
+        const int q = seg_search(C.chpre, C.nseg, b);
+        if (q != cur_q) {
+            sq = load_os_seg(C, q);
+            cur_q = q;
+        }
+        const i64 bl = b - C.chpre[q];
+        const i64 r = C.rpre[q] + bl / RNG;
+        const i64 p0 = sq.first + bl * C.pblk;
+        const i64 p1 = min(sq.first + (sq.n_q + PART - 1) / PART, p0 + C.pblk);
+        if (bl % RNG == 0) rz[r * RADIX + threadIdx.x] = 0;
+        __syncthreads();
+        for (i64 p = p0; p < p1; p += 2) {
+            K key[2][IPT];
+            int n[2];
 #pragma unroll
-        for (int k = 0; k < SCAN_CH; k++) v[k] = p0 + k < p1 ? C.pcnt[(p0 + k) * RADIX + d] : 0;
-        u64 t = 0;
+            for (int h = 0; h < 2; h++) {
+                const i64 c = p + h - sq.first;
+                n[h] = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
 #pragma unroll
-        for (int k = 0; k < SCAN_CH; k++) t += v[k];
-        C.ctot[ch * RADIX + d] = t;
-    }
-}
-
-__global__ __launch_bounds__(NTHREADS) void k_scan_l2(Ctx C) {
-    __shared__ u64 s_scan[NTHREADS / 64];
-    const int d = threadIdx.x;
-    for (int q = blockIdx.x; q < C.nseg; q += gridDim.x) {
-        const i64 c0 = C.chpre[q], c1 = C.chpre[q + 1];
-        u64 run = 0;
-        for (i64 cb = c0; cb < c1; cb += SCAN_CH) {
-            // a batch of chunk totals in flight together, then scanned in registers
-            u64 v[SCAN_CH];
-#pragma unroll
-            for (int k = 0; k < SCAN_CH; k++) v[k] = cb + k < c1 ? C.ctot[(cb + k) * RADIX + d] : 0;
-#pragma unroll
-            for (int k = 0; k < SCAN_CH; k++) {
-                if (cb + k < c1) C.ctot[(cb + k) * RADIX + d] = run;
-                run += v[k];
+                for (int k = 0; k < IPT; k++) {
+                    const int idx = (int)threadIdx.x + k * NTHREADS;
+                    if constexpr (GEN) key[h][k] = idx < n[h] ? raw_key_os<K>(sq, ck, (u32)(c * PART + idx)) : (K)0;
+                    else key[h][k] = idx < n[h] ? kin[sq.lo + c * PART + idx] : (K)0;
+                }
             }
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+#pragma unroll
+                for (int k = 0; k < IPT; k++)
+                    if ((int)threadIdx.x + k * NTHREADS < n[h]) atomicAdd(&s_h[(u32)(key[h][k] >> shift) & (RADIX - 1)], 1u);
         }
-        u64 all;
-        C.pbase[(i64)q * RADIX + d] = (u64)C.segs[q].stage_base + block_excl_scan<u64>(run, s_scan, all);
+        __syncthreads();
+        const u32 v = s_h[threadIdx.x];
+        C.ctot[b * RADIX + threadIdx.x] = v;
+        if (v) atomicAdd((unsigned long long *)&rt[r * RADIX + threadIdx.x], (unsigned long long)v);
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_scan_l3(Ctx C) {
+// First position per digit (thread d) of local block bl of product q: the
+// digit base plus the counts of the earlier ranges and of the range's
+// earlier blocks, loaded in batches.  Whole workgroup.
+__device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 stage_base, u64 *s_scan64) {
+    constexpr int B = 16;
     const int d = threadIdx.x;
-    for (i64 ch = blockIdx.x; ch < C.chpre[C.nseg]; ch += gridDim.x) {
-        int q;
-        i64 p0, p1;
-        chunk_range(C, ch, q, p0, p1);
-        u64 run = C.ctot[ch * RADIX + d] + C.pbase[(i64)q * RADIX + d];
-        u64 v[SCAN_CH];
+    const u64 *rtot = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
+    const i64 b0 = C.chpre[q];
+    const i64 r0 = C.rpre[q], nr = C.rpre[q + 1] - r0;
+    const i64 r = bl / RNG;
+    u64 before = 0, total = 0;
+    for (i64 rr = 0; rr < nr; rr += B) {
+        u64 v[B];
 #pragma unroll
-        for (int k = 0; k < SCAN_CH; k++) v[k] = p0 + k < p1 ? C.pcnt[(p0 + k) * RADIX + d] : 0;
+        for (int k = 0; k < B; k++) v[k] = rr + k < nr ? rtot[(r0 + rr + k) * RADIX + d] : 0;
 #pragma unroll
-        for (int k = 0; k < SCAN_CH; k++) {
-            if (p0 + k < p1) C.pcnt[(p0 + k) * RADIX + d] = run;
-            run += v[k];
+        for (int k = 0; k < B; k++) {
+            total += v[k];
+            if (rr + k < r) before += v[k];
         }
     }
-}
-
-// Digit offsets of product q for one pass: s_base[d] = stage_base + number of
-// the product's keys with a smaller digit.  Whole workgroup.
-__device__ inline void seg_digit_bases(Ctx &C, int pass, int q, u64 *s_base, u64 *s_scan64) {
-    const int d = threadIdx.x;  // RADIX == NTHREADS
-    const u64 h = C.hist[((i64)pass * C.nseg + q) * RADIX + d];
-    u64 tot;
-    const u64 off = block_excl_scan<u64>(h, s_scan64, tot);
-    s_base[d] = (u64)C.segs[q].stage_base + off;
+    for (i64 bb = r * RNG; bb < bl; bb += B) {
+        u64 v[B];
+#pragma unroll
+        for (int k = 0; k < B; k++) v[k] = bb + k < bl ? C.ctot[(b0 + bb + k) * RADIX + d] : 0;
+#pragma unroll
+        for (int k = 0; k < B; k++) before += v[k];
+    }
+    u64 all;
+    return stage_base + block_excl_scan<u64>(total, s_scan64, all) + before;
 }
 
 // ---------------------------------------------------------------------------
 // k_onesweep: one stable LSD radix pass over digit `pass` of every product's
 // staged keys, carrying a payload V (the coefficient for SEG_COMBINE, the
-// pair index for SEG_RAW).  Partition = PART consecutive items of one
-// product.  Ranks come from per-wave ballot "match" masks (peers with the same
-// digit) and per-wave digit counters in LDS; a digit's product-wide position
-// is its digit offset plus a decoupled look-back over the product's earlier
-// partitions.  The partition publishes its digit counts as soon as they are
-// known and resolves its prefix only after the LDS-local reorder, so that
-// the predecessors have published by then.  GEN: pass 0 of SEG_RAW, where
-// items are generated from the pair index instead of read.  The histogram of
-// the next digit is counted on the way (input and output are the same
-// multiset).  FULL partitions (PART items) take a body without item guards.
+// pair index for SEG_RAW).  A workgroup takes one sort block at a time and
+// its partitions (PART consecutive items) in order.  Ranks come from per-wave
+// ballot "match" masks (peers with the same digit) and per-wave digit
+// counters in LDS; a digit's position is the block's running position for
+// that digit, which starts from k_block_scan's offsets and grows by each
+// partition's digit count.  GEN: pass 0 of SEG_RAW, where items are
+// generated from the pair index instead of read.
 // ---------------------------------------------------------------------------
 template <typename K, typename V>
 struct OsSmem {
@@ -551,22 +512,18 @@ struct OsSmem {
     u32 wh[NW][RADIX];
     u32 loff[RADIX];
     i64 goff[RADIX];
-    u64 base[RADIX];
-    u32 nh[RADIX];
     u32 scan[NW];
     u64 scan64[NW];
-    i64 p, pn;
 };
 
 // Items past the end of a partial partition carry the all-ones key: they rank
 // last in the last digit, i.e. at sorted positions [n, PART), so the valid
-// items' positions are unaffected; only that digit's published count and the
-// global writes account for them.
-template <typename K, typename V, bool GEN, bool PRE>
-__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, i64 p, i64 first,
-                                             i64 c, i64 lo, i64 span, int n, const K *__restrict__ kin,
-                                             const V *__restrict__ vin, K *__restrict__ kout, V *__restrict__ vout,
-                                             bool next_hist, u32 *ticket) {
+// items' positions are unaffected; only that digit's count and the global
+// writes account for them.
+template <typename K, typename V, bool GEN>
+__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, i64 c, i64 lo,
+                                             i64 span, int n, const K *__restrict__ kin, const V *__restrict__ vin,
+                                             K *__restrict__ kout, V *__restrict__ vout, u64 &run) {
     constexpr int NW = OsSmem<K, V>::NW;
     const int shift = pass * RADIX_BITS;
     // an opaque copy of the thread index: keeps the per-item index and
@@ -575,7 +532,6 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
     const u32 lane = (u32)tid & 63u, w = (u32)tid >> 6;
-    const u32 tag = (u32)pass + 1;
     const i64 start = lo + c * PART;
     const K *ckeys = (const K *)C.ck;
     const int wbase = (int)w * 64 * IPT + (int)lane;
@@ -623,11 +579,10 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         const u32 old = S.wh[w][d];
         if (before == 0) S.wh[w][d] = old + (u32)__popcll(peers);
         rk[k] = old + before;
-        if (next_hist && wbase + k * 64 < n)
-            atomicAdd(&S.nh[(u32)((key[k] >> (shift + RADIX_BITS)) & (RADIX - 1))], 1u);
     }
     __syncthreads();
-    // digit totals, wave prefixes, local digit offsets; publish the totals
+    // digit totals, wave prefixes, local digit offsets; this partition's
+    // digit positions from the block's running positions
     const int d = tid;  // RADIX == NTHREADS
     u32 tot = 0;
 #pragma unroll
@@ -639,8 +594,9 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     u32 all;
     const u32 loff = block_excl_scan<u32>(tot, S.scan, all);
     if (d == RADIX - 1) tot -= (u32)(PART - n);
-    if constexpr (!PRE) lb_publish(C.look + p * RADIX + d, first, p, tag, tot);
     S.loff[d] = loff;
+    S.goff[d] = (i64)run - (i64)loff;
+    run += tot;
     __syncthreads();
     // keys into LDS in sorted order
 #pragma unroll
@@ -651,16 +607,6 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         S.buf.k[pos] = key[k];
         S.dig[pos] = (unsigned char)dk;
     }
-    // product-wide offset of this digit in this partition: precomputed, or
-    // the digit base plus a look-back over the product's earlier partitions
-    if constexpr (PRE) {
-        S.goff[d] = (i64)C.pcnt[p * RADIX + d] - (i64)loff;
-    } else {
-        const u64 prefix = lookback_batched_resolve(C.look + d, RADIX, first, p, tag, tot, &C.counters[CNT_ERR_SPIN]);
-        S.goff[d] = (i64)(S.base[d] + prefix) - (i64)loff;
-    }
-    u32 tk = 0;
-    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition, claimed while this one scatters
     __syncthreads();
     bool bad = false;
 #pragma unroll
@@ -686,47 +632,35 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         }
     }
     if (bad) atomicOr(&C.counters[CNT_ERR_SPIN], 2u);
-    if (threadIdx.x == 0) S.pn = (i64)tk;
     __syncthreads();
 }
 
-template <typename K, typename V, bool GEN, bool PRE>
+template <typename K, typename V, bool GEN>
 __global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
     constexpr int NW = OsSmem<K, V>::NW;
     __shared__ OsSmem<K, V> S;
-    const bool next_hist = pass + 1 < C.passes;
-    const i64 nparts = C.ppre[C.nseg];
-    u32 *ticket = &C.counters[CNT_SORT + pass];
-    for (int d = threadIdx.x; d < RADIX; d += NTHREADS) S.nh[d] = 0;
-    if (threadIdx.x == 0) S.p = (i64)atomicAdd(ticket, 1u);
-    __syncthreads();
-    i64 p = S.p;
+    const i64 nblk = C.chpre[C.nseg];
     int cur_q = -1;
     OsSeg sq{};
-    while (p < nparts) {
-        for (int d = threadIdx.x; d < NW * RADIX; d += NTHREADS) (&S.wh[0][0])[d] = 0;
-        // partitions come in queue order: the current product still holds p
-        // unless p has reached the next product's first partition
-        const int q = (cur_q >= 0 && p < sq.first + (sq.n_q + PART - 1) / PART) ? cur_q : seg_search(C.ppre, C.nseg, p);
+    for (i64 b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int q = seg_search(C.chpre, C.nseg, b);
         if (q != cur_q) {
-            __syncthreads();
-            if (cur_q >= 0 && next_hist) hist_flush(C, S.nh, pass + 1, cur_q);
-            if constexpr (!PRE) seg_digit_bases(C, pass, q, S.base, S.scan64);
             sq = load_os_seg(C, q);
             cur_q = q;
         }
-        __syncthreads();
-        const i64 c = p - sq.first;
-        const int n = (int)min((i64)PART, sq.n_q - c * PART);
-        os_partition<K, V, GEN, PRE>(C, S, sq, pass, p, sq.first, c, sq.lo, sq.n_q, n, kin, vin, kout, vout, next_hist,
-                                     ticket);
-        p = S.pn;
-    }
-    if (cur_q >= 0 && next_hist) {
-        __syncthreads();
-        hist_flush(C, S.nh, pass + 1, cur_q);
+        const i64 bl = b - C.chpre[q];
+        const i64 p0 = sq.first + bl * C.pblk;
+        const i64 p1 = min(sq.first + (sq.n_q + PART - 1) / PART, p0 + C.pblk);
+        u64 run = block_start(C, pass, q, bl, (u64)sq.lo, S.scan64);
+        for (i64 p = p0; p < p1; p++) {
+            for (int e = threadIdx.x; e < NW * RADIX; e += NTHREADS) (&S.wh[0][0])[e] = 0;
+            __syncthreads();
+            const i64 c = p - sq.first;
+            const int n = (int)min((i64)PART, sq.n_q - c * PART);
+            os_partition<K, V, GEN>(C, S, sq, pass, c, sq.lo, sq.n_q, n, kin, vin, kout, vout, run);
+        }
     }
 }
 
@@ -1327,29 +1261,20 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         ProfScope ps("seg_prepare", st);
         hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
     }
-    const int g = grid_for(P.nparts_bound, cus * 3);
+    const int nblk_bound = (int)std::min<int64_t>(P.nparts_bound / P.pblk + P.nseg + 1, (int64_t)cus * 16);
+    const int g = std::max(1, std::min(nblk_bound, cus * 3));
     K *ka = (K *)C.stA_k, *kb = (K *)C.stB_k;
     V *va = (V *)C.stA_v, *vb = (V *)C.stB_v;
-    if (P.raw && P.passes > 0) {
+    for (int pass = 0; pass < P.passes; pass++) {
+        const bool gen = P.raw && pass == 0;
         {
-            ProfScope ps("hist_raw", st);
-            hipLaunchKernelGGL((k_hist_raw<K>), dim3(grid_for(P.nparts_bound, cus * 8)), dim3(NTHREADS), 0, st, C);
+            ProfScope ps("count", st);
+            if (gen) hipLaunchKernelGGL((k_count<K, true>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, 0, ka);
+            else hipLaunchKernelGGL((k_count<K, false>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka);
         }
-        {
-            ProfScope ps("part_scan", st);
-            const int gc = grid_for(P.nparts_bound / SCAN_CH + P.nseg + 1, cus * 4);
-            hipLaunchKernelGGL(k_scan_l1, dim3(gc), dim3(NTHREADS), 0, st, C);
-            hipLaunchKernelGGL(k_scan_l2, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C);
-            hipLaunchKernelGGL(k_scan_l3, dim3(gc), dim3(NTHREADS), 0, st, C);
-        }
-        ProfScope ps("onesweep_gen", st);
-        hipLaunchKernelGGL((k_onesweep<K, V, true, true>), dim3(g), dim3(NTHREADS), 0, st, C, 0, ka, va, kb, vb);
-        std::swap(ka, kb);
-        std::swap(va, vb);
-    }
-    for (int pass = (P.raw ? 1 : 0); pass < P.passes; pass++) {
-        ProfScope ps("onesweep", st);
-        hipLaunchKernelGGL((k_onesweep<K, V, false, false>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
+        ProfScope ps(gen ? "onesweep_gen" : "onesweep", st);
+        if (gen) hipLaunchKernelGGL((k_onesweep<K, V, true>), dim3(g), dim3(NTHREADS), 0, st, C, 0, ka, va, kb, vb);
+        else hipLaunchKernelGGL((k_onesweep<K, V, false>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
@@ -1453,12 +1378,12 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.stB_k = b + P.o_stBk;
     C.stB_v = b + P.o_stBv;
     C.box = (u64 *)(b + P.o_box);
-    C.hist = (unsigned long long *)(b + P.o_hist);
-    C.look = (u64 *)(b + P.o_look);
     C.pcnt = (u64 *)(b + P.o_pcnt);
     C.ctot = (u64 *)(b + P.o_ctot);
     C.chpre = (i64 *)(b + P.o_chpre);
-    C.pbase = (u64 *)(b + P.o_pbase);
+    C.rpre = (i64 *)(b + P.o_rpre);
+    C.rtot = (u64 *)(b + P.o_rtot);
+    C.nrng = P.nrng;
     C.look_red = (u64 *)(b + P.o_look_red);
     C.look_cmp = (u64 *)(b + P.o_look_cmp);
     C.look_tile = (u64 *)(b + P.o_look_tile);
@@ -1469,6 +1394,7 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.nvars = P.nvars;
     C.bits = P.bits;
     C.passes = P.passes;
+    C.pblk = P.pblk;
     C.ring = P.ring;
     C.ntiles = P.ntiles;
     C.raw = P.raw;

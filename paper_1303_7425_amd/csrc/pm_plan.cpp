@@ -311,19 +311,22 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     const size_t zero0 = off;
     P.o_dyn = take(sizeof(DevSegDyn) * S);
     P.o_counters = take(4 * CNT_COUNT);
-    P.o_hist = take((size_t)8 * std::max(1, P.passes) * S * RADIX);
-    P.o_look = take((size_t)8 * RADIX * std::max<int64_t>(1, P.nparts_bound));
     P.o_look_red = take((size_t)8 * std::max<int64_t>(1, P.nparts_bound));
     P.o_look_cmp = take((size_t)8 * std::max<int64_t>(1, P.ndparts));
     P.o_look_tile = take((size_t)8 * std::max<int64_t>(1, P.ntiles));
     P.o_box = take((size_t)8 * std::max<int64_t>(1, nbox));
+    // range counters of the radix passes, two sets by pass parity (zeroed here,
+    // then each counting kernel clears the other set for the next pass)
+    P.pblk = std::max<int64_t>(1, (P.nparts_bound + (int64_t)cus * 3 - 1) / ((int64_t)cus * 3));
+    P.nrng = (P.nparts_bound / P.pblk + S + 1) / RNG + S + 1;
+    P.o_rtot = take((size_t)8 * RADIX * 2 * P.nrng);
     P.r_zero.off = zero0;
     P.r_zero.bytes = off - zero0;
     P.o_ppre = take((size_t)8 * (S + 1));
     P.o_chpre = take((size_t)8 * (S + 1));
-    P.o_pbase = take((size_t)8 * RADIX * S);
-    P.o_pcnt = take((size_t)8 * RADIX * std::max<int64_t>(1, P.nparts_bound));
-    P.o_ctot = take((size_t)8 * RADIX * (P.nparts_bound / SCAN_CH + S + 1));
+    P.o_rpre = take((size_t)8 * (S + 1));
+    P.o_pcnt = take((size_t)8 * std::max<int64_t>(1, P.nparts_bound));
+    P.o_ctot = take((size_t)8 * RADIX * (P.nparts_bound / P.pblk + S + 1));
     P.o_iv_samp = take((size_t)P.ksize * std::max<int64_t>(1, P.iv_nsamp));
     P.o_iv_spl = take((size_t)P.ksize * std::max<int64_t>(1, P.iv_nspl));
     P.o_iv_cur = take((size_t)4 * std::max<int64_t>(1, (int64_t)P.iv_grid * P.iv_maxrows));

@@ -61,6 +61,7 @@ struct Plan {
     std::vector<int64_t> tile_pre, dpart_pre, cpre;
     std::vector<int32_t> tile_seg, dseg;
     int64_t ntiles = 0, ndparts = 0, nparts_bound = 0;
+    int64_t pblk = 1;   // sort partitions per sort block (blocks about fill the resident grid)
     int raw = 1;        // sparse products sort (key, pair index); else (key, coefficient)
     int nival = 0;      // products on the output-key interval path
     std::vector<int64_t> iv_pre;
@@ -73,10 +74,11 @@ struct Plan {
     // workspace layout
     Region r_stats, r_flags, r_desc, r_zero;
     size_t o_segs = 0, o_vars = 0, o_tile_pre = 0, o_tile_seg = 0, o_dpart_pre = 0, o_dseg = 0, o_cpre = 0;
-    size_t o_dyn = 0, o_counters = 0, o_hist = 0, o_look = 0, o_look_red = 0, o_look_cmp = 0, o_look_tile = 0, o_box = 0;
+    size_t o_dyn = 0, o_counters = 0, o_look_red = 0, o_look_cmp = 0, o_look_tile = 0, o_box = 0;
     size_t o_iv_samp = 0, o_iv_spl = 0, o_iv_cur = 0, o_iv_items = 0, o_iv_off = 0, o_iv_pre = 0, o_iv_seg = 0;
     size_t o_ppre = 0, o_ck = 0, o_stAk = 0, o_stAv = 0, o_stBk = 0, o_stBv = 0;
-    size_t o_pcnt = 0, o_ctot = 0, o_chpre = 0, o_pbase = 0;
+    size_t o_pcnt = 0, o_ctot = 0, o_rtot = 0, o_chpre = 0, o_rpre = 0;
+    int64_t nrng = 1;         // range rows of the radix-pass counters
     size_t total = 0;
 };
 
