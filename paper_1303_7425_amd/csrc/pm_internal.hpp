@@ -31,6 +31,8 @@ constexpr int NTHREADS = 256;          // threads per workgroup (4 wave64s)
 constexpr int IPT = 16;                // items per thread in sort / reduce partitions
 constexpr int PART = NTHREADS * IPT;   // items per partition
 constexpr int RNG = 64;                // sort blocks per range
+constexpr int PBLK_MAX = 16;           // sort partitions per sort block, at most
+constexpr int RSUM_MAX = 16;           // products with at most this many ranges need no range scan
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
@@ -128,6 +130,8 @@ struct Ctx {
     u64 *ctot;                  // digit counts of the current radix pass per sort block [nblocks][RADIX]
     u64 *rtot;                  // the same per range of RNG blocks [2][nrng][RADIX], by pass parity
     i64 nrng;                   // range rows per parity
+    u64 *pbase;                 // [nseg][RADIX] digit bases of the current radix pass
+    i32 rscan;                  // k_range_scan runs (some product may have more than RSUM_MAX ranges)
     i64 *chpre;                 // [nseg+1] sort-block prefix over products (device computed)
     i64 *rpre;                  // [nseg+1] range prefix over products (device computed)
     u64 *look_red;              // reduce lookback [nparts_bound]

@@ -398,9 +398,9 @@ __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
 // its range's counter (rtot, one set per pass parity).  A radix pass
 // takes one block at a time: its first position per digit is the digit base
 // (keys of the product with a smaller digit) plus the counts of the earlier
-// ranges and of the range's earlier blocks; it then ranks the block's
-// partitions in order and carries the positions itself.  No look-back between
-// workgroups and no work queue.
+// ranges (k_range_scan) and of the range's earlier blocks; it then ranks the
+// block's partitions in order and carries the positions itself.  No look-back
+// between workgroups; a work queue over blocks balances uneven products.
 // ---------------------------------------------------------------------------
 // Digit counts of one sort block (digit `pass`; GEN: digit 0 of SEG_RAW pair
 // keys generated on the fly), two partitions per step so that their loads are
@@ -458,36 +458,72 @@ __global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__
     }
 }
 
-// First position per digit (thread d) of local block bl of product q: the
-// digit base plus the counts of the earlier ranges and of the range's
-// earlier blocks, loaded in batches.  Whole workgroup.
-__device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 stage_base, u64 *s_scan64) {
+// Per product: the ranges' counters of this pass become each range's first
+// position per digit inside the product (exclusive prefix over the product's
+// ranges, in place), and the digit bases (stage_base + keys with a smaller
+// digit) go to pbase.  Range loads in batches.
+__global__ __launch_bounds__(NTHREADS) void k_range_scan(Ctx C, int pass) {
     constexpr int B = 16;
-    const int d = threadIdx.x;
-    const u64 *rtot = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
-    const i64 b0 = C.chpre[q];
-    const i64 r0 = C.rpre[q], nr = C.rpre[q + 1] - r0;
-    const i64 r = bl / RNG;
-    u64 before = 0, total = 0;
-    for (i64 rr = 0; rr < nr; rr += B) {
-        u64 v[B];
+    __shared__ u64 s_scan[NTHREADS / 64];
+    u64 *rt = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
+    const int d = threadIdx.x;  // RADIX == NTHREADS
+    for (int q = blockIdx.x; q < C.nseg; q += gridDim.x) {
+        const i64 r0 = C.rpre[q], r1 = C.rpre[q + 1];
+        u64 run = 0;
+        for (i64 rr = r0; rr < r1; rr += B) {
+            u64 v[B];
 #pragma unroll
-        for (int k = 0; k < B; k++) v[k] = rr + k < nr ? rtot[(r0 + rr + k) * RADIX + d] : 0;
+            for (int k = 0; k < B; k++) v[k] = rr + k < r1 ? rt[(rr + k) * RADIX + d] : 0;
 #pragma unroll
-        for (int k = 0; k < B; k++) {
-            total += v[k];
-            if (rr + k < r) before += v[k];
+            for (int k = 0; k < B; k++) {
+                if (rr + k < r1) rt[(rr + k) * RADIX + d] = run;
+                run += v[k];
+            }
         }
+        u64 all;
+        C.pbase[(i64)q * RADIX + d] = (u64)C.segs[q].stage_base + block_excl_scan<u64>(run, s_scan, all);
+    }
+}
+
+// First position per digit (thread d) of local block bl of product q: digit
+// base + the range's first position + the counts of the range's earlier
+// blocks (at most RNG - 1 loads, in batches).  Without the range scan (every
+// product has at most RSUM_MAX ranges) the digit bases and the range's first
+// position are summed here from the product's range counters.  Whole
+// workgroup (a block scan).
+__device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 stage_base, u64 *s_scan64) {
+    constexpr int B = 8;
+    const int d = threadIdx.x;
+    const u64 *rt = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
+    const i64 b0 = C.chpre[q], r0 = C.rpre[q];
+    const i64 r = bl / RNG;
+    u64 pos;
+    if (C.rscan) {
+        pos = C.pbase[(i64)q * RADIX + d] + rt[(r0 + r) * RADIX + d];
+    } else {
+        const i64 nr = C.rpre[q + 1] - r0;  // at most RSUM_MAX
+        u64 before = 0, total = 0;
+        for (int k0 = 0; k0 < RSUM_MAX; k0 += B) {
+            u64 v[B];
+#pragma unroll
+            for (int k = 0; k < B; k++) v[k] = k0 + k < nr ? rt[(r0 + k0 + k) * RADIX + d] : 0;
+#pragma unroll
+            for (int k = 0; k < B; k++) {
+                total += v[k];
+                if (k0 + k < r) before += v[k];
+            }
+        }
+        u64 all;
+        pos = stage_base + block_excl_scan<u64>(total, s_scan64, all) + before;
     }
     for (i64 bb = r * RNG; bb < bl; bb += B) {
         u64 v[B];
 #pragma unroll
         for (int k = 0; k < B; k++) v[k] = bb + k < bl ? C.ctot[(b0 + bb + k) * RADIX + d] : 0;
 #pragma unroll
-        for (int k = 0; k < B; k++) before += v[k];
+        for (int k = 0; k < B; k++) pos += v[k];
     }
-    u64 all;
-    return stage_base + block_excl_scan<u64>(total, s_scan64, all) + before;
+    return pos;
 }
 
 // ---------------------------------------------------------------------------
@@ -636,15 +672,22 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
 }
 
 template <typename K, typename V, bool GEN>
-__global__ __launch_bounds__(NTHREADS) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
     constexpr int NW = OsSmem<K, V>::NW;
     __shared__ OsSmem<K, V> S;
+    __shared__ i64 s_b;
     const i64 nblk = C.chpre[C.nseg];
     int cur_q = -1;
     OsSeg sq{};
-    for (i64 b = blockIdx.x; b < nblk; b += gridDim.x) {
+    while (true) {
+        // blocks are independent: the queue only balances uneven products
+        if (threadIdx.x == 0) s_b = (i64)atomicAdd(&C.counters[CNT_SORT + pass], 1u);
+        __syncthreads();
+        const i64 b = s_b;
+        __syncthreads();
+        if (b >= nblk) break;
         const int q = seg_search(C.chpre, C.nseg, b);
         if (q != cur_q) {
             sq = load_os_seg(C, q);
@@ -1271,6 +1314,7 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
             ProfScope ps("count", st);
             if (gen) hipLaunchKernelGGL((k_count<K, true>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, 0, ka);
             else hipLaunchKernelGGL((k_count<K, false>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka);
+            if (P.rscan) hipLaunchKernelGGL(k_range_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C, pass);
         }
         ProfScope ps(gen ? "onesweep_gen" : "onesweep", st);
         if (gen) hipLaunchKernelGGL((k_onesweep<K, V, true>), dim3(g), dim3(NTHREADS), 0, st, C, 0, ka, va, kb, vb);
@@ -1384,6 +1428,8 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.rpre = (i64 *)(b + P.o_rpre);
     C.rtot = (u64 *)(b + P.o_rtot);
     C.nrng = P.nrng;
+    C.pbase = (u64 *)(b + P.o_pbase);
+    C.rscan = P.rscan;
     C.look_red = (u64 *)(b + P.o_look_red);
     C.look_cmp = (u64 *)(b + P.o_look_cmp);
     C.look_tile = (u64 *)(b + P.o_look_tile);

@@ -317,14 +317,22 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_box = take((size_t)8 * std::max<int64_t>(1, nbox));
     // range counters of the radix passes, two sets by pass parity (zeroed here,
     // then each counting kernel clears the other set for the next pass)
-    P.pblk = std::max<int64_t>(1, (P.nparts_bound + (int64_t)cus * 3 - 1) / ((int64_t)cus * 3));
+    P.pblk = std::max<int64_t>(1, std::min<int64_t>(PBLK_MAX, (P.nparts_bound + (int64_t)cus * 3 - 1) / ((int64_t)cus * 3)));
     P.nrng = (P.nparts_bound / P.pblk + S + 1) / RNG + S + 1;
+    P.rscan = 0;
+    for (int q = 0; q < S; q++) {
+        const DevSeg &d = P.segs[q];
+        if (d.mode != SEG_RAW && d.mode != SEG_COMBINE) continue;
+        const int64_t np = (d.stage_bound + PART - 1) / PART, nb = (np + P.pblk - 1) / P.pblk;
+        if ((nb + RNG - 1) / RNG > RSUM_MAX) P.rscan = 1;
+    }
     P.o_rtot = take((size_t)8 * RADIX * 2 * P.nrng);
     P.r_zero.off = zero0;
     P.r_zero.bytes = off - zero0;
     P.o_ppre = take((size_t)8 * (S + 1));
     P.o_chpre = take((size_t)8 * (S + 1));
     P.o_rpre = take((size_t)8 * (S + 1));
+    P.o_pbase = take((size_t)8 * RADIX * S);
     P.o_pcnt = take((size_t)8 * std::max<int64_t>(1, P.nparts_bound));
     P.o_ctot = take((size_t)8 * RADIX * (P.nparts_bound / P.pblk + S + 1));
     P.o_iv_samp = take((size_t)P.ksize * std::max<int64_t>(1, P.iv_nsamp));

@@ -235,6 +235,19 @@ def test_cancellation_with_capacity_below_slots():
     assert np.array_equal(got[0], wk) and np.array_equal(got[1], wc)
 
 
+def test_sort_blocks_with_range_scan():
+    # one product of 68.9e6 term pairs on the sort path: more than 16 x 64 sort
+    # blocks, so the radix passes take their block positions from the range
+    # scan (the large sparse workload stays below that and sums its ranges)
+    pm = _pm()
+    pm.set_tuning(-1, 0, False)
+    rng = W.rng_for(78)
+    f = W.random_sparse(rng, 8300, 6, 10, 6, "modp")
+    g = W.random_sparse(rng, 8300, 6, 10, 6, "modp")
+    check(f, g, "range scan")
+    assert pm.last_call_info()["staged"] == len(f) * len(g)
+
+
 def test_single_variable_full_width():
     # one variable, 64-bit field: the degree box is not compressible
     rng = np.random.default_rng(5)
