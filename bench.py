@@ -42,9 +42,13 @@ def measured_traffic(label):
 KERNEL_LABELS = [
     ("k_onesweep<unsigned int, unsigned int, false>", "onesweep pass (reads staged items)"),
     ("k_onesweep<unsigned int, unsigned int, true>", "onesweep pass 0 (generates items)"),
+    ("k_count<unsigned int, false>", "count (staged keys)"),
+    ("k_count<unsigned int, true>", "count (generated keys)"),
+    ("k_range_scan", "range_scan"),
+    ("k_head_count<", "head_count"),
+    ("k_head_scan", "head_scan"),
     ("k_reduce<", "reduce"),
     ("k_zero_compact<", "zero_compact"),
-    ("k_hist_raw<", "hist_raw"),
     ("k_seg_prepare", "seg_prepare"),
     ("k_stats", "stats"),
     ("k_compress<", "compress"),
