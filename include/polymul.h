@@ -109,9 +109,9 @@ int pm_mul_bound(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, 
 
 /*
  * h = f * g.  `workspace` is device memory of at least the size returned by
- * pm_mul_bound for the same operands (256-byte aligned).  Returns PM_OK once
- * the product is enqueued on `stream`, or an error code (nothing enqueued
- * that writes h).
+ * pm_mul_bound for the same operands, 256-byte aligned (else PM_EINVAL).
+ * Returns PM_OK once the product is enqueued on `stream`, or an error code
+ * (nothing enqueued that writes h).
  */
 int pm_mul(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
            int64_t workspace_bytes, void *stream);
@@ -120,7 +120,8 @@ int pm_mul(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const 
  * Batched form: `count` independent products h[k] = f[k] * g[k] sharing one
  * layout, run from a single device work queue of tiles (persistent kernels,
  * replayed from a HIP graph).  max_terms[k] receives each product's bound;
- * workspace_bytes the size pm_mul_batch needs for the whole batch.
+ * workspace_bytes the size pm_mul_batch needs for the whole batch.  The
+ * workspace is 256-byte aligned, as for pm_mul (else PM_EINVAL).
  */
 int pm_mul_batch_bound(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
                        int64_t *max_terms, int64_t *workspace_bytes, void *stream);

@@ -247,6 +247,7 @@ int mul_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f
     if (count == 0) return PM_OK;
     const size_t need0 = stats_region_bytes((int)count, (int)L->nvars) + sizeof(DevSeg) * count;
     if (!ws || ws_bytes < (int64_t)need0) return PM_ENOMEM;
+    if ((uintptr_t)ws & 255) return PM_EINVAL;  // kernels use 16-byte loads from workspace regions
     Plan P;
     int rc = stats_and_plan(hs, L, count, f, g, ws, st, tune, P);
     if (rc) return rc;
@@ -320,6 +321,7 @@ int pm_batch_prepare(const pm_layout *layout, int64_t count, const pm_cpoly *f, 
     hipStream_t st = (hipStream_t)stream;
     const size_t need0 = stats_region_bytes((int)count, (int)layout->nvars) + sizeof(DevSeg) * count;
     if (!workspace || workspace_bytes < (int64_t)need0) return PM_ENOMEM;
+    if ((uintptr_t)workspace & 255) return PM_EINVAL;
     pm_batch *b = new pm_batch();
     rc = stats_and_plan(g_stage, layout, count, f, g, workspace, st, g_tune, b->plan);
     if (!rc && (int64_t)b->plan.total > workspace_bytes) rc = PM_ENOMEM;

@@ -430,25 +430,72 @@ __global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__
         const i64 p1 = min(sq.first + (sq.n_q + PART - 1) / PART, p0 + C.pblk);
         if (bl % RNG == 0) rz[r * RADIX + threadIdx.x] = 0;
         __syncthreads();
-        for (i64 p = p0; p < p1; p += 2) {
-            K key[2][IPT];
-            int n[2];
+        if constexpr (GEN) {
+            for (i64 p = p0; p < p1; p += 2) {
+                K key[2][IPT];
+                int n[2];
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const i64 c = p + h - sq.first;
-                n[h] = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
+                for (int h = 0; h < 2; h++) {
+                    const i64 c = p + h - sq.first;
+                    n[h] = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
 #pragma unroll
-                for (int k = 0; k < IPT; k++) {
-                    const int idx = (int)threadIdx.x + k * NTHREADS;
-                    if constexpr (GEN) key[h][k] = idx < n[h] ? raw_key_os<K>(sq, ck, (u32)(c * PART + idx)) : (K)0;
-                    else key[h][k] = idx < n[h] ? kin[sq.lo + c * PART + idx] : (K)0;
+                    for (int k = 0; k < IPT; k++) {
+                        const int idx = (int)threadIdx.x + k * NTHREADS;
+                        key[h][k] = idx < n[h] ? raw_key_os<K>(sq, ck, (u32)(c * PART + idx)) : (K)0;
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; h++)
+#pragma unroll
+                    for (int k = 0; k < IPT; k++)
+                        if ((int)threadIdx.x + k * NTHREADS < n[h])
+                            atomicAdd(&s_h[(u32)(key[h][k] >> shift) & (RADIX - 1)], 1u);
+            }
+        } else {
+            // Staged keys: each thread takes IPT consecutive keys (16-byte
+            // loads; products start on 64-item boundaries) and counts runs of
+            // equal digits in a register, so the LDS sees one add per run.
+            // After the low digits are sorted, neighbouring keys mostly share
+            // their high digits, and per-item adds would collide in LDS.
+            constexpr int VW = 16 / (int)sizeof(K);
+            for (i64 p = p0; p < p1; p += 2) {
+                K key[2][IPT];
+                int nv[2];
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const i64 c = p + h - sq.first;
+                    const int n = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
+                    nv[h] = min(max(n - (int)threadIdx.x * IPT, 0), IPT);
+                    const K *src = kin + sq.lo + c * PART + (i64)threadIdx.x * IPT;
+                    if (nv[h] == IPT) {
+#pragma unroll
+                        for (int k = 0; k < IPT; k += VW) {
+                            const uint4 w = *(const uint4 *)(src + k);
+                            __builtin_memcpy(&key[h][k], &w, 16);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < IPT; k++) key[h][k] = k < nv[h] ? src[k] : (K)0;
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    u32 prev = (u32)(key[h][0] >> shift) & (RADIX - 1), cnt = 0;
+#pragma unroll
+                    for (int k = 0; k < IPT; k++) {
+                        const u32 dk = (u32)(key[h][k] >> shift) & (RADIX - 1);
+                        if (k < nv[h]) {
+                            if (dk != prev) {
+                                atomicAdd(&s_h[prev], cnt);
+                                prev = dk;
+                                cnt = 0;
+                            }
+                            cnt++;
+                        }
+                    }
+                    if (cnt) atomicAdd(&s_h[prev], cnt);
                 }
             }
-#pragma unroll
-            for (int h = 0; h < 2; h++)
-#pragma unroll
-                for (int k = 0; k < IPT; k++)
-                    if ((int)threadIdx.x + k * NTHREADS < n[h]) atomicAdd(&s_h[(u32)(key[h][k] >> shift) & (RADIX - 1)], 1u);
         }
         __syncthreads();
         const u32 v = s_h[threadIdx.x];
@@ -540,42 +587,32 @@ __device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 sta
 template <typename K, typename V>
 struct OsSmem {
     static constexpr int NW = NTHREADS / 64;
-    union {
-        K k[PART];
-        V v[PART];
-    } buf;
-    unsigned char dig[PART];
+    static constexpr int OCC = os_resident((int)sizeof(K), (int)sizeof(V));  // waves per SIMD
+    K k[PART];
+    V v[PART];
     u32 wh[NW][RADIX];
     u32 loff[RADIX];
-    i64 goff[RADIX];
+    u32 goff[RADIX];  // digit's first position minus its local offset, from the product start, mod 2^32
     u32 scan[NW];
     u64 scan64[NW];
 };
 
-// Items past the end of a partial partition carry the all-ones key: they rank
-// last in the last digit, i.e. at sorted positions [n, PART), so the valid
-// items' positions are unaffected; only that digit's count and the global
-// writes account for them.
+// Loads partition c (n items, warp-striped: item k of lane l in wave w is
+// w*64*IPT + k*64 + l) into registers.  Items past the end of a partial
+// partition carry the all-ones key: they rank last in the last digit, i.e. at
+// sorted positions [n, PART), so the valid items' positions are unaffected;
+// only that digit's count and the global writes account for them.
 template <typename K, typename V, bool GEN>
-__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, i64 c, i64 lo,
-                                             i64 span, int n, const K *__restrict__ kin, const V *__restrict__ vin,
-                                             K *__restrict__ kout, V *__restrict__ vout, u64 &run) {
-    constexpr int NW = OsSmem<K, V>::NW;
-    const int shift = pass * RADIX_BITS;
+__device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int n, const K *__restrict__ kin,
+                                        const V *__restrict__ vin, K (&key)[IPT], V (&val)[IPT]) {
     // an opaque copy of the thread index: keeps the per-item index and
-    // address arithmetic inside the partition loop instead of holding sixteen
-    // of each in registers for the whole kernel
+    // address arithmetic here instead of holding sixteen of each in
+    // registers for the whole kernel
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const u32 lane = (u32)tid & 63u, w = (u32)tid >> 6;
-    const i64 start = lo + c * PART;
+    const int wbase = (tid >> 6) * 64 * IPT + (tid & 63);
+    const i64 start = s.lo + c * PART;
     const K *ckeys = (const K *)C.ck;
-    const int wbase = (int)w * 64 * IPT + (int)lane;
-
-    // load, warp-striped: item k of lane l in wave w is w*64*IPT + k*64 + l
-    K key[IPT];
-    V val[IPT];
-    u32 rk[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
         const int idx = wbase + k * 64;
@@ -588,33 +625,59 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         }
     }
     if constexpr (!GEN) {
-        // payloads are only permuted: issue their loads now so they overlap the ranking
 #pragma unroll
         for (int k = 0; k < IPT; k++) {
             const int idx = wbase + k * 64;
             val[k] = idx < n ? vin[start + idx] : (V)0;
         }
     }
-    // per-wave stable ranking: a lane's peers are the lanes whose digit equals
-    // its own; per digit bit, the ballot of lanes with the bit set XOR this
-    // lane's bit broadcast to all ones or zeros marks the lanes that differ
-    // (every lane of the wave is active here: missing items carry a key)
+}
+
+// One partition (c, n items) whose items are in key/val.  Ranks them, places
+// them in LDS in sorted order, then, while the sorted items are written out,
+// loads the next partition (cn, nn items; nn = 0: none) into key/val.  `run`
+// (thread d) is digit d's next position in the staging buffer.  Expects the
+// wave digit counters S.wh zeroed and leaves them zeroed.
+template <typename K, typename V, bool GEN>
+__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, int n, i64 cn,
+                                             int nn, const K *__restrict__ kin, const V *__restrict__ vin,
+                                             K *__restrict__ kout, V *__restrict__ vout, K (&key)[IPT],
+                                             V (&val)[IPT], u64 &run) {
+    constexpr int NW = OsSmem<K, V>::NW;
+    const int shift = pass * RADIX_BITS;
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const u32 w = (u32)tid >> 6;
+    u32 rk[IPT];
+    // Per-wave stable ranking.  A lane's peers are the lanes whose digit
+    // equals its own: per digit bit, the ballot of lanes with the bit set,
+    // XNOR this lane's bit widened to all ones or zeros, keeps the lanes that
+    // agree (every lane is active here: missing items carry a key).  Each
+    // lane reads its digit's wave counter, and the first lane of each peer
+    // group adds the group's size without waiting for the value (a wave's
+    // LDS operations stay in order, so the next slot reads the sum).
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
         const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
-        u32 mis_lo = 0, mis_hi = 0;
+        u32 t[RADIX_BITS];
+        u64 m[RADIX_BITS];
 #pragma unroll
         for (int b = 0; b < RADIX_BITS; b++) {
-            const u32 t = (u32)((i32)(d << (31 - b)) >> 31);
-            const u64 m = __ballot(t != 0);
-            mis_lo |= (u32)m ^ t;
-            mis_hi |= (u32)(m >> 32) ^ t;
+            t[b] = (u32)((i32)(d << (31 - b)) >> 31);
+            asm volatile("" : "+v"(t[b]));  // the ballot tests t itself, which the masks reuse
         }
-        const u64 peers = ~(((u64)mis_hi << 32) | mis_lo);
-        const u32 before = mbcnt(peers);
-        const u32 old = S.wh[w][d];
-        if (before == 0) S.wh[w][d] = old + (u32)__popcll(peers);
-        rk[k] = old + before;
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; b++) m[b] = __ballot(t[b] != 0);
+        // peers & ~(t ^ m): truth table 0x84 over (t, peers, m)
+        u32 pl = ~0u, ph = ~0u;
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; b++) {
+            pl = __builtin_amdgcn_bitop3_b32(t[b], pl, (u32)m[b], 0x84);
+            ph = __builtin_amdgcn_bitop3_b32(t[b], ph, (u32)(m[b] >> 32), 0x84);
+        }
+        const u32 before = __builtin_amdgcn_mbcnt_hi(ph, __builtin_amdgcn_mbcnt_lo(pl, 0u));
+        rk[k] = S.wh[w][d] + before;
+        if (before == 0) atomicAdd(&S.wh[w][d], (u32)(__popc(pl) + __popc(ph)));
     }
     __syncthreads();
     // digit totals, wave prefixes, local digit offsets; this partition's
@@ -631,40 +694,54 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     const u32 loff = block_excl_scan<u32>(tot, S.scan, all);
     if (d == RADIX - 1) tot -= (u32)(PART - n);
     S.loff[d] = loff;
-    S.goff[d] = (i64)run - (i64)loff;
+    S.goff[d] = (u32)(run - (u64)s.lo) - loff;
     run += tot;
     __syncthreads();
-    // keys into LDS in sorted order
+    // keys and payloads into LDS in sorted order
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
         const u32 dk = (u32)((key[k] >> shift) & (RADIX - 1));
         const u32 pos = S.loff[dk] + S.wh[w][dk] + rk[k];
-        rk[k] = pos;
-        S.buf.k[pos] = key[k];
-        S.dig[pos] = (unsigned char)dk;
+        S.k[pos] = key[k];
+        S.v[pos] = val[k];
     }
     __syncthreads();
+    if (nn > 0) os_load<K, V, GEN>(C, s, cn, nn, kin, vin, key, val);
+#pragma unroll
+    for (int ww = 0; ww < NW; ww++) S.wh[ww][d] = 0;
+    // sorted item i of digit d goes to goff[d] + i; a position outside the
+    // product (only possible with inconsistent counts) is flagged, and in a
+    // full partition clamped so that the stores stay unconditional
+    K *kq = kout + s.lo;
+    V *vq = vout + s.lo;
+    const u32 span32 = (u32)s.n_q;
     bool bad = false;
+    if (n == PART) {
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
-        const int i = tid + k * NTHREADS;
-        if (i < n) {
-            const i64 o = S.goff[S.dig[i]] + i;
-            const bool ok = (u64)(o - lo) < (u64)span;
-            if (ok) kout[o] = S.buf.k[i];
-            bad |= !ok;
+        for (int k = 0; k < IPT; k++) {
+            const u32 i = (u32)tid + (u32)(k * NTHREADS);
+            const K kv = S.k[i];
+            const V vv = S.v[i];
+            u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
+            bad |= rel >= span32;
+            rel = min(rel, span32 - 1u);
+            kq[rel] = kv;
+            vq[rel] = vv;
         }
-    }
-    __syncthreads();
+    } else {
 #pragma unroll
-    for (int k = 0; k < IPT; k++) S.buf.v[rk[k]] = val[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < IPT; k++) {
-        const int i = tid + k * NTHREADS;
-        if (i < n) {
-            const i64 o = S.goff[S.dig[i]] + i;
-            if ((u64)(o - lo) < (u64)span) vout[o] = S.buf.v[i];
+        for (int k = 0; k < IPT; k++) {
+            const u32 i = (u32)tid + (u32)(k * NTHREADS);
+            if (i < (u32)n) {
+                const K kv = S.k[i];
+                const u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
+                if (rel < span32) {
+                    kq[rel] = kv;
+                    vq[rel] = S.v[i];
+                } else {
+                    bad = true;
+                }
+            }
         }
     }
     if (bad) atomicOr(&C.counters[CNT_ERR_SPIN], 2u);
@@ -672,7 +749,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
 }
 
 template <typename K, typename V, bool GEN>
-__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
     constexpr int NW = OsSmem<K, V>::NW;
@@ -681,6 +758,9 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
     const i64 nblk = C.chpre[C.nseg];
     int cur_q = -1;
     OsSeg sq{};
+    for (int e = threadIdx.x; e < NW * RADIX; e += NTHREADS) (&S.wh[0][0])[e] = 0;
+    K key[IPT];
+    V val[IPT];
     while (true) {
         // blocks are independent: the queue only balances uneven products
         if (threadIdx.x == 0) s_b = (i64)atomicAdd(&C.counters[CNT_SORT + pass], 1u);
@@ -694,15 +774,14 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
             cur_q = q;
         }
         const i64 bl = b - C.chpre[q];
-        const i64 p0 = sq.first + bl * C.pblk;
-        const i64 p1 = min(sq.first + (sq.n_q + PART - 1) / PART, p0 + C.pblk);
+        const i64 c0 = bl * C.pblk;
+        const i64 c1 = min((sq.n_q + PART - 1) / PART, c0 + C.pblk);
+        os_load<K, V, GEN>(C, sq, c0, (int)min((i64)PART, sq.n_q - c0 * PART), kin, vin, key, val);
         u64 run = block_start(C, pass, q, bl, (u64)sq.lo, S.scan64);
-        for (i64 p = p0; p < p1; p++) {
-            for (int e = threadIdx.x; e < NW * RADIX; e += NTHREADS) (&S.wh[0][0])[e] = 0;
-            __syncthreads();
-            const i64 c = p - sq.first;
+        for (i64 c = c0; c < c1; c++) {
             const int n = (int)min((i64)PART, sq.n_q - c * PART);
-            os_partition<K, V, GEN>(C, S, sq, pass, c, sq.lo, sq.n_q, n, kin, vin, kout, vout, run);
+            const int nn = c + 1 < c1 ? (int)min((i64)PART, sq.n_q - (c + 1) * PART) : 0;
+            os_partition<K, V, GEN>(C, S, sq, pass, n, c + 1, nn, kin, vin, kout, vout, key, val, run);
         }
     }
 }
@@ -1305,7 +1384,7 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
     }
     const int nblk_bound = (int)std::min<int64_t>(P.nparts_bound / P.pblk + P.nseg + 1, (int64_t)cus * 16);
-    const int g = std::max(1, std::min(nblk_bound, cus * 3));
+    const int g = std::max(1, std::min(nblk_bound, cus * os_resident((int)sizeof(K), (int)sizeof(V))));
     K *ka = (K *)C.stA_k, *kb = (K *)C.stB_k;
     V *va = (V *)C.stA_v, *vb = (V *)C.stB_v;
     for (int pass = 0; pass < P.passes; pass++) {

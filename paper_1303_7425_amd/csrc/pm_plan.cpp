@@ -248,7 +248,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             d.nb_div = make_div32((uint32_t)d.nb);
             d.stage_base = nstage;
             d.stage_bound = d.na * d.nb;
-            nstage += d.stage_bound;
+            nstage += (d.stage_bound + 63) & ~(int64_t)63;
             d.iv_samp_off = P.iv_nsamp;
             P.iv_nsamp += (d.iv_l + 1) * (d.iv_l + 1);
             d.iv_spl_off = P.iv_nspl;
@@ -262,7 +262,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         if (d.mode == SEG_COMBINE || d.mode == SEG_RAW) {
             d.stage_base = nstage;
             d.stage_bound = d.na * d.nb;
-            nstage += d.stage_bound;
+            nstage += (d.stage_bound + 63) & ~(int64_t)63;  // products start on 64-item boundaries
             P.nparts_bound += (d.stage_bound + PART - 1) / PART;
             P.nsparse++;
         }
@@ -317,7 +317,8 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_box = take((size_t)8 * std::max<int64_t>(1, nbox));
     // range counters of the radix passes, two sets by pass parity (zeroed here,
     // then each counting kernel clears the other set for the next pass)
-    P.pblk = std::max<int64_t>(1, std::min<int64_t>(PBLK_MAX, (P.nparts_bound + (int64_t)cus * 3 - 1) / ((int64_t)cus * 3)));
+    const int64_t resident = (int64_t)cus * os_resident(P.ksize, P.vsize);
+    P.pblk = std::max<int64_t>(1, std::min<int64_t>(PBLK_MAX, (P.nparts_bound + resident - 1) / resident));
     P.nrng = (P.nparts_bound / P.pblk + S + 1) / RNG + S + 1;
     P.rscan = 0;
     for (int q = 0; q < S; q++) {

@@ -291,6 +291,29 @@ def test_validation_errors_match_oracle():
     assert e.value.code == pm.PM_ERANGE
 
 
+def test_misaligned_workspace_rejected():
+    """The workspace must be 256-byte aligned (kernels issue 16-byte loads
+    from its regions); an offset pointer is refused before anything runs."""
+    pm = _pm()
+    import ctypes
+    import torch
+    f, g = W.config3("modp", n=3)
+    lay = pm.make_layout(5, 12, "modp")
+    df, dg = pm.to_device(f), pm.to_device(g)
+    cap, wb = pm.bound(lay, df, dg)
+    hk, hc, hn = pm.alloc_out(cap, "modp")
+    h = pm.pm_poly(cap, hn.data_ptr(), hk.data_ptr(), hc.data_ptr())
+    ws = torch.empty(wb + 512, dtype=torch.uint8, device="cuda")
+    for off, code in ((16, pm.PM_EINVAL), (256, pm.PM_OK)):
+        rc = pm.lib().pm_mul(ctypes.byref(lay), ctypes.byref(pm._cpoly(df)), ctypes.byref(pm._cpoly(dg)),
+                             ctypes.byref(h), ctypes.c_void_p(ws.data_ptr() + off), wb, None)
+        assert rc == code, (off, rc)
+    torch.cuda.synchronize()
+    want = oracle.mul(f, g)
+    assert int(hn.item()) == len(want[0])
+    assert np.array_equal(hk[:len(want[0])].cpu().numpy().view(np.uint64), want[0])
+
+
 def test_truncation_reports_full_count():
     pm = _pm()
     import torch
