@@ -33,9 +33,9 @@ constexpr int PART = NTHREADS * IPT;   // items per partition
 constexpr int RNG = 64;                // sort blocks per range
 constexpr int PBLK_MAX = 16;           // sort partitions per sort block, at most
 constexpr int RSUM_MAX = 16;           // products with at most this many ranges need no range scan
-// Radix-pass workgroups resident per CU: four when keys and payloads are
-// 4 bytes each (LDS and registers allow it), else two.
-constexpr int os_resident(int ksize, int vsize) { return ksize + vsize <= 8 ? 4 : 2; }
+// Radix-pass workgroups (512 threads) resident per CU: three when keys and
+// payloads are 4 bytes each (LDS and registers allow it), else two.
+constexpr int os_resident(int ksize, int vsize) { return ksize + vsize <= 8 ? 3 : 2; }
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;

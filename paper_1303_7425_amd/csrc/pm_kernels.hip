@@ -538,37 +538,43 @@ __global__ __launch_bounds__(NTHREADS) void k_range_scan(Ctx C, int pass) {
 // product has at most RSUM_MAX ranges) the digit bases and the range's first
 // position are summed here from the product's range counters.  Whole
 // workgroup (a block scan).
+template <int NT>
 __device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 stage_base, u64 *s_scan64) {
     constexpr int B = 8;
     const int d = threadIdx.x;
+    const bool dig = d < RADIX;
     const u64 *rt = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
     const i64 b0 = C.chpre[q], r0 = C.rpre[q];
     const i64 r = bl / RNG;
     u64 pos;
     if (C.rscan) {
-        pos = C.pbase[(i64)q * RADIX + d] + rt[(r0 + r) * RADIX + d];
+        pos = dig ? C.pbase[(i64)q * RADIX + d] + rt[(r0 + r) * RADIX + d] : 0;
     } else {
         const i64 nr = C.rpre[q + 1] - r0;  // at most RSUM_MAX
         u64 before = 0, total = 0;
-        for (int k0 = 0; k0 < RSUM_MAX; k0 += B) {
-            u64 v[B];
+        if (dig) {
+            for (int k0 = 0; k0 < RSUM_MAX; k0 += B) {
+                u64 v[B];
 #pragma unroll
-            for (int k = 0; k < B; k++) v[k] = k0 + k < nr ? rt[(r0 + k0 + k) * RADIX + d] : 0;
+                for (int k = 0; k < B; k++) v[k] = k0 + k < nr ? rt[(r0 + k0 + k) * RADIX + d] : 0;
 #pragma unroll
-            for (int k = 0; k < B; k++) {
-                total += v[k];
-                if (k0 + k < r) before += v[k];
+                for (int k = 0; k < B; k++) {
+                    total += v[k];
+                    if (k0 + k < r) before += v[k];
+                }
             }
         }
         u64 all;
-        pos = stage_base + block_excl_scan<u64>(total, s_scan64, all) + before;
+        pos = stage_base + block_excl_scan<u64, NT>(total, s_scan64, all) + before;
     }
-    for (i64 bb = r * RNG; bb < bl; bb += B) {
-        u64 v[B];
+    if (dig) {
+        for (i64 bb = r * RNG; bb < bl; bb += B) {
+            u64 v[B];
 #pragma unroll
-        for (int k = 0; k < B; k++) v[k] = bb + k < bl ? C.ctot[(b0 + bb + k) * RADIX + d] : 0;
+            for (int k = 0; k < B; k++) v[k] = bb + k < bl ? C.ctot[(b0 + bb + k) * RADIX + d] : 0;
 #pragma unroll
-        for (int k = 0; k < B; k++) pos += v[k];
+            for (int k = 0; k < B; k++) pos += v[k];
+        }
     }
     return pos;
 }
@@ -584,10 +590,13 @@ __device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 sta
 // partition's digit count.  GEN: pass 0 of SEG_RAW, where items are
 // generated from the pair index instead of read.
 // ---------------------------------------------------------------------------
+constexpr int OS_T = 512;            // radix-pass workgroup: 8 waves
+constexpr int OS_IPT = PART / OS_T;  // items per thread
+
 template <typename K, typename V>
 struct OsSmem {
-    static constexpr int NW = NTHREADS / 64;
-    static constexpr int OCC = os_resident((int)sizeof(K), (int)sizeof(V));  // waves per SIMD
+    static constexpr int NW = OS_T / 64;
+    static constexpr int OCC = os_resident((int)sizeof(K), (int)sizeof(V)) * OS_T / 256;  // waves per SIMD
     K k[PART];
     V v[PART];
     u32 wh[NW][RADIX];
@@ -598,23 +607,23 @@ struct OsSmem {
 };
 
 // Loads partition c (n items, warp-striped: item k of lane l in wave w is
-// w*64*IPT + k*64 + l) into registers.  Items past the end of a partial
+// w*64*OS_IPT + k*64 + l) into registers.  Items past the end of a partial
 // partition carry the all-ones key: they rank last in the last digit, i.e. at
 // sorted positions [n, PART), so the valid items' positions are unaffected;
 // only that digit's count and the global writes account for them.
 template <typename K, typename V, bool GEN>
 __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int n, const K *__restrict__ kin,
-                                        const V *__restrict__ vin, K (&key)[IPT], V (&val)[IPT]) {
+                                        const V *__restrict__ vin, K (&key)[OS_IPT], V (&val)[OS_IPT]) {
     // an opaque copy of the thread index: keeps the per-item index and
     // address arithmetic here instead of holding sixteen of each in
     // registers for the whole kernel
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const int wbase = (tid >> 6) * 64 * IPT + (tid & 63);
+    const int wbase = (tid >> 6) * 64 * OS_IPT + (tid & 63);
     const i64 start = s.lo + c * PART;
     const K *ckeys = (const K *)C.ck;
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
+    for (int k = 0; k < OS_IPT; k++) {
         const int idx = wbase + k * 64;
         if constexpr (GEN) {
             const u32 x = (u32)(c * PART + idx);
@@ -626,7 +635,7 @@ __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int
     }
     if constexpr (!GEN) {
 #pragma unroll
-        for (int k = 0; k < IPT; k++) {
+        for (int k = 0; k < OS_IPT; k++) {
             const int idx = wbase + k * 64;
             val[k] = idx < n ? vin[start + idx] : (V)0;
         }
@@ -641,14 +650,14 @@ __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int
 template <typename K, typename V, bool GEN>
 __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, int n, i64 cn,
                                              int nn, const K *__restrict__ kin, const V *__restrict__ vin,
-                                             K *__restrict__ kout, V *__restrict__ vout, K (&key)[IPT],
-                                             V (&val)[IPT], u64 &run) {
+                                             K *__restrict__ kout, V *__restrict__ vout, K (&key)[OS_IPT],
+                                             V (&val)[OS_IPT], u64 &run) {
     constexpr int NW = OsSmem<K, V>::NW;
     const int shift = pass * RADIX_BITS;
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
     const u32 w = (u32)tid >> 6;
-    u32 rk[IPT];
+    u32 rk[OS_IPT];
     // Per-wave stable ranking.  A lane's peers are the lanes whose digit
     // equals its own: per digit bit, the ballot of lanes with the bit set,
     // XNOR this lane's bit widened to all ones or zeros, keeps the lanes that
@@ -657,7 +666,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     // group adds the group's size without waiting for the value (a wave's
     // LDS operations stay in order, so the next slot reads the sum).
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
+    for (int k = 0; k < OS_IPT; k++) {
         const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
         u32 t[RADIX_BITS];
         u64 m[RADIX_BITS];
@@ -680,26 +689,32 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         if (before == 0) atomicAdd(&S.wh[w][d], (u32)(__popc(pl) + __popc(ph)));
     }
     __syncthreads();
-    // digit totals, wave prefixes, local digit offsets; this partition's
-    // digit positions from the block's running positions
-    const int d = tid;  // RADIX == NTHREADS
+    // digit totals, wave prefixes, local digit offsets (thread d < RADIX
+    // holds digit d); this partition's digit positions from the block's
+    // running positions
+    const int d = tid;
+    const bool dig = d < RADIX;
     u32 tot = 0;
+    if (dig) {
 #pragma unroll
-    for (int ww = 0; ww < NW; ww++) {
-        const u32 x = S.wh[ww][d];
-        S.wh[ww][d] = tot;
-        tot += x;
+        for (int ww = 0; ww < NW; ww++) {
+            const u32 x = S.wh[ww][d];
+            S.wh[ww][d] = tot;
+            tot += x;
+        }
     }
     u32 all;
-    const u32 loff = block_excl_scan<u32>(tot, S.scan, all);
-    if (d == RADIX - 1) tot -= (u32)(PART - n);
-    S.loff[d] = loff;
-    S.goff[d] = (u32)(run - (u64)s.lo) - loff;
-    run += tot;
+    const u32 loff = block_excl_scan<u32, OS_T>(tot, S.scan, all);
+    if (dig) {
+        if (d == RADIX - 1) tot -= (u32)(PART - n);
+        S.loff[d] = loff;
+        S.goff[d] = (u32)(run - (u64)s.lo) - loff;
+        run += tot;
+    }
     __syncthreads();
     // keys and payloads into LDS in sorted order
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
+    for (int k = 0; k < OS_IPT; k++) {
         const u32 dk = (u32)((key[k] >> shift) & (RADIX - 1));
         const u32 pos = S.loff[dk] + S.wh[w][dk] + rk[k];
         S.k[pos] = key[k];
@@ -708,7 +723,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     __syncthreads();
     if (nn > 0) os_load<K, V, GEN>(C, s, cn, nn, kin, vin, key, val);
 #pragma unroll
-    for (int ww = 0; ww < NW; ww++) S.wh[ww][d] = 0;
+    for (int e = 0; e < NW * RADIX / OS_T; e++) (&S.wh[0][0])[tid + e * OS_T] = 0;
     // sorted item i of digit d goes to goff[d] + i; a position outside the
     // product (only possible with inconsistent counts) is flagged, and in a
     // full partition clamped so that the stores stay unconditional
@@ -718,8 +733,8 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     bool bad = false;
     if (n == PART) {
 #pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            const u32 i = (u32)tid + (u32)(k * NTHREADS);
+        for (int k = 0; k < OS_IPT; k++) {
+            const u32 i = (u32)tid + (u32)(k * OS_T);
             const K kv = S.k[i];
             const V vv = S.v[i];
             u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
@@ -730,8 +745,8 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            const u32 i = (u32)tid + (u32)(k * NTHREADS);
+        for (int k = 0; k < OS_IPT; k++) {
+            const u32 i = (u32)tid + (u32)(k * OS_T);
             if (i < (u32)n) {
                 const K kv = S.k[i];
                 const u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
@@ -749,7 +764,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
 }
 
 template <typename K, typename V, bool GEN>
-__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
+__global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
     constexpr int NW = OsSmem<K, V>::NW;
@@ -758,9 +773,9 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(OsSmem
     const i64 nblk = C.chpre[C.nseg];
     int cur_q = -1;
     OsSeg sq{};
-    for (int e = threadIdx.x; e < NW * RADIX; e += NTHREADS) (&S.wh[0][0])[e] = 0;
-    K key[IPT];
-    V val[IPT];
+    for (int e = threadIdx.x; e < NW * RADIX; e += OS_T) (&S.wh[0][0])[e] = 0;
+    K key[OS_IPT];
+    V val[OS_IPT];
     while (true) {
         // blocks are independent: the queue only balances uneven products
         if (threadIdx.x == 0) s_b = (i64)atomicAdd(&C.counters[CNT_SORT + pass], 1u);
@@ -777,7 +792,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(OsSmem
         const i64 c0 = bl * C.pblk;
         const i64 c1 = min((sq.n_q + PART - 1) / PART, c0 + C.pblk);
         os_load<K, V, GEN>(C, sq, c0, (int)min((i64)PART, sq.n_q - c0 * PART), kin, vin, key, val);
-        u64 run = block_start(C, pass, q, bl, (u64)sq.lo, S.scan64);
+        u64 run = block_start<OS_T>(C, pass, q, bl, (u64)sq.lo, S.scan64);
         for (i64 c = c0; c < c1; c++) {
             const int n = (int)min((i64)PART, sq.n_q - c * PART);
             const int nn = c + 1 < c1 ? (int)min((i64)PART, sq.n_q - (c + 1) * PART) : 0;
@@ -1396,8 +1411,8 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
             if (P.rscan) hipLaunchKernelGGL(k_range_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C, pass);
         }
         ProfScope ps(gen ? "onesweep_gen" : "onesweep", st);
-        if (gen) hipLaunchKernelGGL((k_onesweep<K, V, true>), dim3(g), dim3(NTHREADS), 0, st, C, 0, ka, va, kb, vb);
-        else hipLaunchKernelGGL((k_onesweep<K, V, false>), dim3(g), dim3(NTHREADS), 0, st, C, pass, ka, va, kb, vb);
+        if (gen) hipLaunchKernelGGL((k_onesweep<K, V, true>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+        else hipLaunchKernelGGL((k_onesweep<K, V, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
