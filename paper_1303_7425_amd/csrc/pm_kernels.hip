@@ -10,7 +10,8 @@
 //   k_count      digit counts per sort block before each radix pass
 //   k_onesweep   one stable LSD radix pass (8-bit digit); a workgroup ranks one
 //                sort block's partitions in order from precomputed positions;
-//                pass 0 of SEG_RAW generates its keys from the operands
+//                SEG_RAW products sort pair indices alone and regenerate their
+//                keys from the operands' compressed keys
 //   k_head_count run heads per reduce partition, k_head_scan their prefix
 //   k_reduce     segmented like-term reduction + key decompression
 //   k_zero_compact removal of runs that cancelled to zero
@@ -402,105 +403,145 @@ __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
 // block's partitions in order and carries the positions itself.  No look-back
 // between workgroups; a work queue over blocks balances uneven products.
 // ---------------------------------------------------------------------------
-// Digit counts of one sort block (digit `pass`; GEN: digit 0 of SEG_RAW pair
-// keys generated on the fly), two partitions per step so that their loads are
-// in flight together.  Writes the block's histogram, adds it into its range's
-// counter of this pass's parity, and clears the other parity's row of the
-// range for the next pass (the first block of each range does).
-template <typename K, bool GEN>
-__global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__restrict__ kin) {
+// Where a radix pass takes its items from.  SM_STAGED: (key, payload) pairs
+// in the staging buffers (LDS-combined products).  SEG_RAW products carry
+// only the pair index x = i*nb + j, whose key ck(alpha_i) + ck(beta_j) is
+// regenerated from the compressed operand keys (a few tens of KB, cache
+// resident) whenever it is needed: SM_GEN (first pass) takes x from the
+// position, SM_INDEX (later passes) reads x from the staging buffer.
+enum { SM_STAGED = 0, SM_GEN = 1, SM_INDEX = 2 };
+
+// Digit counts (digit `pass`) of one sort block, two partitions per step so
+// that their loads are in flight together.  Writes the block's histogram,
+// adds it into its range's counter of this pass's parity, and clears the
+// other parity's row of the range for the next pass (the first block of each
+// range does).  Staged keys and pair indices: each thread takes IPT
+// consecutive items (16-byte loads; products start on 64-item boundaries)
+// and counts runs of equal digits in a register, so the LDS sees one add per
+// run: after the low digits are sorted, neighbouring keys mostly share their
+// high digits, and per-item adds would collide in LDS.  Regenerated keys
+// read the product's compressed operand keys (f's then g's, contiguous) from
+// a copy in LDS when they fit in `lds_ck` entries (the dynamic LDS size),
+// else from global memory: LDS serves a 64-lane gather in a few cycles, the
+// vector cache about one line per cycle.  Generated pair indices run along
+// the lanes, so that the LDS reads of g's keys hit distinct banks.
+template <typename K, int SM>
+__global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__restrict__ kin,
+                                                    const u32 *__restrict__ xin, int lds_ck) {
     __shared__ u32 s_h[RADIX];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    K *s_ck = (K *)s_dyn;
     const int shift = pass * RADIX_BITS;
     u64 *rt = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
     u64 *rz = C.rtot + (i64)((pass + 1) & 1) * C.nrng * RADIX;
     const K *ck = (const K *)C.ck;
     const i64 nblk = C.chpre[C.nseg];
+    const int tid = (int)threadIdx.x;
     int cur_q = -1;
     OsSeg sq{};
+    bool in_lds = false;
     for (i64 b = blockIdx.x; b < nblk; b += gridDim.x) {
-        s_h[threadIdx.x] = 0;  // RADIX == NTHREADS
+        s_h[tid] = 0;  // RADIX == NTHREADS
         const int q = seg_search(C.chpre, C.nseg, b);
         if (q != cur_q) {
             sq = load_os_seg(C, q);
             cur_q = q;
+            if constexpr (SM != SM_STAGED) {
+                const i64 m = sq.ck_g - sq.ck_f + sq.nb;  // f's and g's compressed keys
+                in_lds = m <= lds_ck;
+                if (in_lds) {
+                    __syncthreads();  // the previous product's copy is no longer read
+                    for (i64 t = tid; t < m; t += NTHREADS) s_ck[t] = ck[sq.ck_f + t];
+                }
+            }
         }
         const i64 bl = b - C.chpre[q];
         const i64 r = C.rpre[q] + bl / RNG;
         const i64 p0 = sq.first + bl * C.pblk;
         const i64 p1 = min(sq.first + (sq.n_q + PART - 1) / PART, p0 + C.pblk);
-        if (bl % RNG == 0) rz[r * RADIX + threadIdx.x] = 0;
+        const K *kf = in_lds ? s_ck : ck + sq.ck_f;
+        const K *kg = kf + (sq.ck_g - sq.ck_f);
+        if (bl % RNG == 0) rz[r * RADIX + tid] = 0;
         __syncthreads();
-        if constexpr (GEN) {
-            for (i64 p = p0; p < p1; p += 2) {
-                K key[2][IPT];
-                int n[2];
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const i64 c = p + h - sq.first;
-                    n[h] = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
-#pragma unroll
-                    for (int k = 0; k < IPT; k++) {
-                        const int idx = (int)threadIdx.x + k * NTHREADS;
-                        key[h][k] = idx < n[h] ? raw_key_os<K>(sq, ck, (u32)(c * PART + idx)) : (K)0;
-                    }
-                }
-#pragma unroll
-                for (int h = 0; h < 2; h++)
-#pragma unroll
-                    for (int k = 0; k < IPT; k++)
-                        if ((int)threadIdx.x + k * NTHREADS < n[h])
-                            atomicAdd(&s_h[(u32)(key[h][k] >> shift) & (RADIX - 1)], 1u);
-            }
-        } else {
-            // Staged keys: each thread takes IPT consecutive keys (16-byte
-            // loads; products start on 64-item boundaries) and counts runs of
-            // equal digits in a register, so the LDS sees one add per run.
-            // After the low digits are sorted, neighbouring keys mostly share
-            // their high digits, and per-item adds would collide in LDS.
-            constexpr int VW = 16 / (int)sizeof(K);
-            for (i64 p = p0; p < p1; p += 2) {
-                K key[2][IPT];
-                int nv[2];
+        for (i64 p = p0; p < p1; p += 2) {
+            K key[2][IPT];
+            int nv[2];
+            if constexpr (SM == SM_GEN) {
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
                     const i64 c = p + h - sq.first;
                     const int n = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
-                    nv[h] = min(max(n - (int)threadIdx.x * IPT, 0), IPT);
-                    const K *src = kin + sq.lo + c * PART + (i64)threadIdx.x * IPT;
-                    if (nv[h] == IPT) {
-#pragma unroll
-                        for (int k = 0; k < IPT; k += VW) {
-                            const uint4 w = *(const uint4 *)(src + k);
-                            __builtin_memcpy(&key[h][k], &w, 16);
-                        }
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < IPT; k++) key[h][k] = k < nv[h] ? src[k] : (K)0;
-                    }
-                }
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    u32 prev = (u32)(key[h][0] >> shift) & (RADIX - 1), cnt = 0;
+                    nv[h] = n;  // items tid + k * NTHREADS below n are valid
 #pragma unroll
                     for (int k = 0; k < IPT; k++) {
-                        const u32 dk = (u32)(key[h][k] >> shift) & (RADIX - 1);
-                        if (k < nv[h]) {
-                            if (dk != prev) {
-                                atomicAdd(&s_h[prev], cnt);
-                                prev = dk;
-                                cnt = 0;
+                        const int idx = tid + k * NTHREADS;
+                        const u32 x = (u32)(c * PART + idx);
+                        const u32 i = div32(x, sq.nb_div);
+                        key[h][k] = idx < n ? kf[i] + kg[x - i * sq.nb] : (K)0;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const i64 c = p + h - sq.first;
+                    const int n = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
+                    nv[h] = min(max(n - tid * IPT, 0), IPT);
+                    const i64 at = sq.lo + c * PART + (i64)tid * IPT;
+                    if constexpr (SM == SM_INDEX) {
+                        u32 x[IPT];
+                        if (nv[h] == IPT) {
+#pragma unroll
+                            for (int k = 0; k < IPT; k += 4) {
+                                const uint4 w = *(const uint4 *)(xin + at + k);
+                                __builtin_memcpy(&x[k], &w, 16);
                             }
-                            cnt++;
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < IPT; k++) x[k] = k < nv[h] ? xin[at + k] : 0u;
+                        }
+#pragma unroll
+                        for (int k = 0; k < IPT; k++) {
+                            const u32 i = div32(x[k], sq.nb_div);
+                            key[h][k] = k < nv[h] ? kf[i] + kg[x[k] - i * sq.nb] : (K)0;
+                        }
+                    } else {
+                        constexpr int VW = 16 / (int)sizeof(K);
+                        if (nv[h] == IPT) {
+#pragma unroll
+                            for (int k = 0; k < IPT; k += VW) {
+                                const uint4 w = *(const uint4 *)(kin + at + k);
+                                __builtin_memcpy(&key[h][k], &w, 16);
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < IPT; k++) key[h][k] = k < nv[h] ? kin[at + k] : (K)0;
                         }
                     }
-                    if (cnt) atomicAdd(&s_h[prev], cnt);
                 }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                u32 prev = (u32)(key[h][0] >> shift) & (RADIX - 1), cnt = 0;
+#pragma unroll
+                for (int k = 0; k < IPT; k++) {
+                    const u32 dk = (u32)(key[h][k] >> shift) & (RADIX - 1);
+                    const bool valid = SM == SM_GEN ? tid + k * NTHREADS < nv[h] : k < nv[h];
+                    if (valid) {
+                        if (dk != prev) {
+                            atomicAdd(&s_h[prev], cnt);
+                            prev = dk;
+                            cnt = 0;
+                        }
+                        cnt++;
+                    }
+                }
+                if (cnt) atomicAdd(&s_h[prev], cnt);
             }
         }
         __syncthreads();
-        const u32 v = s_h[threadIdx.x];
-        C.ctot[b * RADIX + threadIdx.x] = v;
-        if (v) atomicAdd((unsigned long long *)&rt[r * RADIX + threadIdx.x], (unsigned long long)v);
+        const u32 v = s_h[tid];
+        C.ctot[b * RADIX + tid] = v;
+        if (v) atomicAdd((unsigned long long *)&rt[r * RADIX + tid], (unsigned long long)v);
         __syncthreads();
     }
 }
@@ -581,14 +622,14 @@ __device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 sta
 
 // ---------------------------------------------------------------------------
 // k_onesweep: one stable LSD radix pass over digit `pass` of every product's
-// staged keys, carrying a payload V (the coefficient for SEG_COMBINE, the
-// pair index for SEG_RAW).  A workgroup takes one sort block at a time and
-// its partitions (PART consecutive items) in order.  Ranks come from per-wave
+// items: (key, coefficient) for SEG_COMBINE, the pair index alone for
+// SEG_RAW (see SM_*).  A workgroup takes one sort block at a time and its
+// partitions (PART consecutive items) in order.  Ranks come from per-wave
 // ballot "match" masks (peers with the same digit) and per-wave digit
 // counters in LDS; a digit's position is the block's running position for
-// that digit, which starts from k_block_scan's offsets and grows by each
-// partition's digit count.  GEN: pass 0 of SEG_RAW, where items are
-// generated from the pair index instead of read.
+// that digit, which starts from block_start's offsets and grows by each
+// partition's digit count.  WK: the pass also writes the keys (always for
+// staged items; for pair indices only in the last pass, for the reduction).
 // ---------------------------------------------------------------------------
 constexpr int OS_T = 512;            // radix-pass workgroup: 8 waves
 constexpr int OS_IPT = PART / OS_T;  // items per thread
@@ -611,7 +652,7 @@ struct OsSmem {
 // partition carry the all-ones key: they rank last in the last digit, i.e. at
 // sorted positions [n, PART), so the valid items' positions are unaffected;
 // only that digit's count and the global writes account for them.
-template <typename K, typename V, bool GEN>
+template <typename K, typename V, int SM>
 __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int n, const K *__restrict__ kin,
                                         const V *__restrict__ vin, K (&key)[OS_IPT], V (&val)[OS_IPT]) {
     // an opaque copy of the thread index: keeps the per-item index and
@@ -622,18 +663,32 @@ __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int
     const int wbase = (tid >> 6) * 64 * OS_IPT + (tid & 63);
     const i64 start = s.lo + c * PART;
     const K *ckeys = (const K *)C.ck;
+    if constexpr (SM == SM_GEN) {
 #pragma unroll
-    for (int k = 0; k < OS_IPT; k++) {
-        const int idx = wbase + k * 64;
-        if constexpr (GEN) {
+        for (int k = 0; k < OS_IPT; k++) {
+            const int idx = wbase + k * 64;
             const u32 x = (u32)(c * PART + idx);
             key[k] = idx < n ? raw_key_os<K>(s, ckeys, x) : ~(K)0;
             val[k] = (V)x;
-        } else {
+        }
+    } else if constexpr (SM == SM_INDEX) {
+#pragma unroll
+        for (int k = 0; k < OS_IPT; k++) {
+            const int idx = wbase + k * 64;
+            val[k] = idx < n ? vin[start + idx] : (V)0;
+        }
+#pragma unroll
+        for (int k = 0; k < OS_IPT; k++) {
+            const int idx = wbase + k * 64;
+            key[k] = idx < n ? raw_key_os<K>(s, ckeys, (u32)val[k]) : ~(K)0;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < OS_IPT; k++) {
+            const int idx = wbase + k * 64;
             key[k] = idx < n ? kin[start + idx] : ~(K)0;
         }
-    }
-    if constexpr (!GEN) {
+        // payloads are only permuted: their loads overlap the ranking
 #pragma unroll
         for (int k = 0; k < OS_IPT; k++) {
             const int idx = wbase + k * 64;
@@ -647,7 +702,7 @@ __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int
 // loads the next partition (cn, nn items; nn = 0: none) into key/val.  `run`
 // (thread d) is digit d's next position in the staging buffer.  Expects the
 // wave digit counters S.wh zeroed and leaves them zeroed.
-template <typename K, typename V, bool GEN>
+template <typename K, typename V, int SM, bool WK>
 __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, int n, i64 cn,
                                              int nn, const K *__restrict__ kin, const V *__restrict__ vin,
                                              K *__restrict__ kout, V *__restrict__ vout, K (&key)[OS_IPT],
@@ -721,7 +776,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         S.v[pos] = val[k];
     }
     __syncthreads();
-    if (nn > 0) os_load<K, V, GEN>(C, s, cn, nn, kin, vin, key, val);
+    if (nn > 0) os_load<K, V, SM>(C, s, cn, nn, kin, vin, key, val);
 #pragma unroll
     for (int e = 0; e < NW * RADIX / OS_T; e++) (&S.wh[0][0])[tid + e * OS_T] = 0;
     // sorted item i of digit d goes to goff[d] + i; a position outside the
@@ -740,7 +795,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
             u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
             bad |= rel >= span32;
             rel = min(rel, span32 - 1u);
-            kq[rel] = kv;
+            if constexpr (WK) kq[rel] = kv;
             vq[rel] = vv;
         }
     } else {
@@ -751,7 +806,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
                 const K kv = S.k[i];
                 const u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
                 if (rel < span32) {
-                    kq[rel] = kv;
+                    if constexpr (WK) kq[rel] = kv;
                     vq[rel] = S.v[i];
                 } else {
                     bad = true;
@@ -763,7 +818,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     __syncthreads();
 }
 
-template <typename K, typename V, bool GEN>
+template <typename K, typename V, int SM, bool WK>
 __global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
@@ -791,12 +846,12 @@ __global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, 
         const i64 bl = b - C.chpre[q];
         const i64 c0 = bl * C.pblk;
         const i64 c1 = min((sq.n_q + PART - 1) / PART, c0 + C.pblk);
-        os_load<K, V, GEN>(C, sq, c0, (int)min((i64)PART, sq.n_q - c0 * PART), kin, vin, key, val);
+        os_load<K, V, SM>(C, sq, c0, (int)min((i64)PART, sq.n_q - c0 * PART), kin, vin, key, val);
         u64 run = block_start<OS_T>(C, pass, q, bl, (u64)sq.lo, S.scan64);
         for (i64 c = c0; c < c1; c++) {
             const int n = (int)min((i64)PART, sq.n_q - c * PART);
             const int nn = c + 1 < c1 ? (int)min((i64)PART, sq.n_q - (c + 1) * PART) : 0;
-            os_partition<K, V, GEN>(C, S, sq, pass, n, c + 1, nn, kin, vin, kout, vout, key, val, run);
+            os_partition<K, V, SM, WK>(C, S, sq, pass, n, c + 1, nn, kin, vin, kout, vout, key, val, run);
         }
     }
 }
@@ -1404,15 +1459,28 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
     V *va = (V *)C.stA_v, *vb = (V *)C.stB_v;
     for (int pass = 0; pass < P.passes; pass++) {
         const bool gen = P.raw && pass == 0;
+        const bool last = pass == P.passes - 1;
         {
             ProfScope ps("count", st);
-            if (gen) hipLaunchKernelGGL((k_count<K, true>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, 0, ka);
-            else hipLaunchKernelGGL((k_count<K, false>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka);
+            if constexpr (sizeof(V) == 4) {  // SEG_RAW: pair indices
+                const int lds_ck = (int)P.ck_lds;
+                const size_t dyn = (size_t)lds_ck * sizeof(K);
+                if (gen) hipLaunchKernelGGL((k_count<K, SM_GEN>), dim3(nblk_bound), dim3(NTHREADS), dyn, st, C, 0, ka, (const u32 *)va, lds_ck);
+                else hipLaunchKernelGGL((k_count<K, SM_INDEX>), dim3(nblk_bound), dim3(NTHREADS), dyn, st, C, pass, ka, (const u32 *)va, lds_ck);
+            } else {
+                hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
+            }
             if (P.rscan) hipLaunchKernelGGL(k_range_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C, pass);
         }
         ProfScope ps(gen ? "onesweep_gen" : "onesweep", st);
-        if (gen) hipLaunchKernelGGL((k_onesweep<K, V, true>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
-        else hipLaunchKernelGGL((k_onesweep<K, V, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+        if constexpr (sizeof(V) == 4) {
+            if (gen && last) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+            else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+            else if (last) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, true>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+            else hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+        } else {
+            hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+        }
         std::swap(ka, kb);
         std::swap(va, vb);
     }

@@ -284,6 +284,14 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.iv_grid = (int)std::max<int64_t>(1, std::min<int64_t>(P.iv_items, (int64_t)cus * 2));
     P.nbox = nbox;
     P.nck = nck;
+    // digit counts of pair-index sorts regenerate keys from an LDS copy of
+    // the product's compressed operand keys, up to 64 KB (two workgroups per
+    // CU); larger products read them from global memory
+    P.ck_lds = 0;
+    for (int q = 0; q < S; q++) {
+        const int64_t m = P.segs[q].na + P.segs[q].nb;
+        if (P.segs[q].mode == SEG_RAW && m * P.ksize <= (64 << 10)) P.ck_lds = std::max<int64_t>(P.ck_lds, m);
+    }
 
     // workspace layout
     size_t off = 0;
