@@ -989,11 +989,14 @@ constexpr u32 TAG_ZCOMPACT = 201u;
 constexpr int RED_T = 512, RED_IPT = PART / RED_T;
 
 template <typename K, typename V, int RING>
-__global__ __launch_bounds__(RED_T) void k_reduce(Ctx C, const K *__restrict__ kin, const V *__restrict__ vin) {
+// three workgroups of 4-byte keys per CU (LDS), two of 8-byte keys
+__global__ __launch_bounds__(RED_T) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 6 : 4))) void k_reduce(Ctx C, const K *__restrict__ kin, const V *__restrict__ vin) {
     constexpr int PADN = PART + PART / 16;
     __shared__ K s_k[PADN];
     __shared__ u64 s_v[PADN];
     __shared__ u32 s_scan[RED_T / 64];
+    __shared__ int s_wp[RED_T / 64];
+    __shared__ u64 s_ws[RED_T / 64];
     __shared__ i64 s_p, s_pn;
     __shared__ u64 s_base;
     __shared__ u32 s_z;
@@ -1081,34 +1084,119 @@ __global__ __launch_bounds__(RED_T) void k_reduce(Ctx C, const K *__restrict__ k
             }
         }
         __syncthreads();
-        // each head sums its run; the sum replaces the head's value in LDS
-        {
-            int open = -1;
-            u64 acc = 0;
+        // each head's run sum replaces the head's value in LDS
+        if constexpr (RING == RING_F64) {
+            // FP64: the head's thread adds its run left to right (the oracle's order)
+            {
+                int open = -1;
+                u64 acc = 0;
+#pragma unroll
+                for (int r = 0; r < RED_IPT; r++) {
+                    if (b0 + r < n) {
+                        const u64 v = s_v[pad(b0 + r)];
+                        if ((hm >> r) & 1) {
+                            if (open >= 0) s_v[pad(b0 + open)] = acc;
+                            open = r;
+                            acc = v;
+                        } else if (open >= 0) {
+                            acc = ring_add<RING>(acc, v);
+                        }
+                    }
+                }
+                if (open >= 0) {
+                    // the last run may continue into the next threads' items and partitions
+                    const K key = s_k[pad(b0 + open)];
+                    int j = b0 + RED_IPT;
+                    while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
+                    if (j >= n && n > 0) {
+                        for (i64 g = start + n; g < send && kin[g] == key; g++)
+                            acc = ring_add<RING>(acc, item_value_rd<K, V, RING>(s, vin[g]));
+                    }
+                    s_v[pad(b0 + open)] = acc;
+                }
+            }
+        } else {
+            // exact rings: a segmented scan over the threads.  Each thread
+            // sums the runs that start and end inside its items, and offers
+            // (position of its last head or -1, sum from there to its end; or
+            // with no head, the sum of all its items); the scan hands each
+            // thread the run still open on its left, which it completes when
+            // it holds a head.  The thread holding the partition's last item
+            // completes the last open run, following it into the next
+            // partitions when it continues there.
+            int lp = -1;
+            u64 ls = 0, pre = 0;
 #pragma unroll
             for (int r = 0; r < RED_IPT; r++) {
                 if (b0 + r < n) {
                     const u64 v = s_v[pad(b0 + r)];
                     if ((hm >> r) & 1) {
-                        if (open >= 0) s_v[pad(b0 + open)] = acc;
-                        open = r;
-                        acc = v;
-                    } else if (open >= 0) {
-                        acc = ring_add<RING>(acc, v);
+                        if (lp >= 0) s_v[pad(lp)] = ls;
+                        lp = b0 + r;
+                        ls = v;
+                    } else if (lp >= 0) {
+                        ls = ring_add<RING>(ls, v);
+                    } else {
+                        pre = ring_add<RING>(pre, v);
                     }
                 }
             }
-            if (open >= 0) {
-                // the last run may continue into the next threads' items and partitions
-                const K key = s_k[pad(b0 + open)];
-                int j = b0 + RED_IPT;
-                while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
-                if (j >= n && n > 0) {
-                    for (i64 g = start + n; g < send && kin[g] == key; g++)
-                        acc = ring_add<RING>(acc, item_value_rd<K, V, RING>(s, vin[g]));
+            // inclusive scan of (p, s): (p1, s1) + (p2, s2) = p2 >= 0 ? (p2, s2) : (p1, s1 + s2)
+            int ip = lp;
+            u64 is = lp >= 0 ? ls : pre;
+            const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int po = __shfl_up(ip, off, 64);
+                const u64 so = __shfl_up(is, off, 64);
+                if (lane >= off && ip < 0) {
+                    ip = po;
+                    is = ring_add<RING>(so, is);
                 }
-                s_v[pad(b0 + open)] = acc;
             }
+            if (lane == 63) {
+                s_wp[wv] = ip;
+                s_ws[wv] = is;
+            }
+            int ep = __shfl_up(ip, 1, 64);
+            u64 es = __shfl_up(is, 1, 64);
+            if (lane == 0) {
+                ep = -1;
+                es = 0;
+            }
+            __syncthreads();
+            // the carry from earlier waves, then this wave's earlier lanes
+            int cp = -1;
+            u64 cs = 0;
+            for (int w2 = 0; w2 < wv; w2++) {
+                if (s_wp[w2] >= 0) {
+                    cp = s_wp[w2];
+                    cs = s_ws[w2];
+                } else {
+                    cs = ring_add<RING>(cs, s_ws[w2]);
+                }
+            }
+            if (ep >= 0) {
+                cp = ep;
+                cs = es;
+            } else {
+                cs = ring_add<RING>(cs, es);
+            }
+            if (lp >= 0 && cp >= 0) s_v[pad(cp)] = ring_add<RING>(cs, pre);  // the open run ends before my first head
+            if (b0 < n && b0 + RED_IPT >= n) {
+                // the partition's last open run: combine the carry with this thread's part
+                int fp = lp >= 0 ? lp : cp;
+                u64 fs = lp >= 0 ? ls : ring_add<RING>(cs, pre);
+                if (fp >= 0) {
+                    const K key = s_k[pad(fp)];
+                    for (i64 g = start + n; g < send && kin[g] == key; g++)
+                        fs = ring_add<RING>(fs, item_value_rd<K, V, RING>(s, vin[g]));
+                    s_v[pad(fp)] = fs;
+                }
+            }
+            // a run still open at this thread's end is completed by the thread
+            // holding the next head or the partition's last item
+            __syncthreads();
         }
         u32 tk = 0;
         if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition
@@ -1472,7 +1560,9 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
             }
             if (P.rscan) hipLaunchKernelGGL(k_range_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C, pass);
         }
-        ProfScope ps(gen ? "onesweep_gen" : "onesweep", st);
+        // profile names: the generating pass, passes that move items only,
+        // and the last pass of a pair-index sort (it also writes the keys)
+        ProfScope ps(gen ? "onesweep_gen" : (P.raw && last) ? "onesweep_last" : "onesweep", st);
         if constexpr (sizeof(V) == 4) {
             if (gen && last) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
             else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
