@@ -213,10 +213,11 @@ int pm_last_call_status(void *stream);
  * synchronising `stream`: items radix-sorted (term pairs, or combined pairs
  * after the LDS tile combine), radix passes, bytes per sort key and per sort
  * payload, and degree-box cells (dense path).  A 4-byte payload is a pair
- * index: those sorts move the index alone and regenerate its key from the
- * operands in each pass; only the last pass also writes keys.  An 8-byte
- * payload is a combined coefficient moved with its key in every pass.  Any
- * pointer may be NULL.
+ * index: while the launch's compressed operand keys total at most 1 MB and
+ * each product's fit in 64 KB, those sorts move the index alone and
+ * regenerate its key from the operands in each pass (only the last pass also
+ * writes keys); otherwise keys move with the index.  An 8-byte payload is a combined coefficient moved with its key
+ * in every pass.  Any pointer may be NULL.
  */
 int pm_last_call_info(void *stream, int64_t *staged_pairs, int32_t *passes, int32_t *key_bytes,
                       int32_t *payload_bytes, int64_t *box_cells);

@@ -1548,13 +1548,18 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
     for (int pass = 0; pass < P.passes; pass++) {
         const bool gen = P.raw && pass == 0;
         const bool last = pass == P.passes - 1;
+        // pair-index sorts regenerate keys (P.ix) while the operands' compressed
+        // keys stay cache resident; otherwise the generating pass writes the
+        // keys and later passes move (key, index) pairs
+        const bool ix = P.raw && P.ix;
         {
             ProfScope ps("count", st);
             if constexpr (sizeof(V) == 4) {  // SEG_RAW: pair indices
                 const int lds_ck = (int)P.ck_lds;
                 const size_t dyn = (size_t)lds_ck * sizeof(K);
                 if (gen) hipLaunchKernelGGL((k_count<K, SM_GEN>), dim3(nblk_bound), dim3(NTHREADS), dyn, st, C, 0, ka, (const u32 *)va, lds_ck);
-                else hipLaunchKernelGGL((k_count<K, SM_INDEX>), dim3(nblk_bound), dim3(NTHREADS), dyn, st, C, pass, ka, (const u32 *)va, lds_ck);
+                else if (ix) hipLaunchKernelGGL((k_count<K, SM_INDEX>), dim3(nblk_bound), dim3(NTHREADS), dyn, st, C, pass, ka, (const u32 *)va, lds_ck);
+                else hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
             } else {
                 hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
             }
@@ -1562,10 +1567,11 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         }
         // profile names: the generating pass, passes that move items only,
         // and the last pass of a pair-index sort (it also writes the keys)
-        ProfScope ps(gen ? "onesweep_gen" : (P.raw && last) ? "onesweep_last" : "onesweep", st);
+        ProfScope ps(gen ? "onesweep_gen" : (ix && last) ? "onesweep_last" : "onesweep", st);
         if constexpr (sizeof(V) == 4) {
-            if (gen && last) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+            if (gen && (last || !ix)) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
             else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+            else if (!ix) hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
             else if (last) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, true>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
             else hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
         } else {

@@ -287,10 +287,19 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     // digit counts of pair-index sorts regenerate keys from an LDS copy of
     // the product's compressed operand keys, up to 64 KB (two workgroups per
     // CU); larger products read them from global memory
+    // Pair-index sorts regenerate each key from the operands' compressed keys
+    // while those stay cache resident (gathers that hit in L2) and every
+    // product's keys fit the digit count's LDS copy; otherwise (over 1 MB of
+    // them in one launch, as in large batches, or a product with more than
+    // 64 KB of them) the generating pass writes the keys and later passes
+    // carry them.
+    P.ix = (int64_t)nck * P.ksize <= (int64_t)1 << 20;
     P.ck_lds = 0;
     for (int q = 0; q < S; q++) {
         const int64_t m = P.segs[q].na + P.segs[q].nb;
-        if (P.segs[q].mode == SEG_RAW && m * P.ksize <= (64 << 10)) P.ck_lds = std::max<int64_t>(P.ck_lds, m);
+        if (P.segs[q].mode != SEG_RAW) continue;
+        if (m * P.ksize <= (64 << 10)) P.ck_lds = std::max<int64_t>(P.ck_lds, m);
+        else P.ix = 0;
     }
 
     // workspace layout

@@ -45,6 +45,21 @@ def test_batch_matches_oracle(ring):
     check_results(pairs, res, ring)
 
 
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_batch_with_large_operand_keys(ring):
+    """More than 1 MB of compressed operand keys in one launch: the pair-index
+    sort carries its keys through the passes instead of regenerating them."""
+    pm = _pm()
+    rng = W.rng_for(77)
+    pairs = [(W.random_sparse(rng, 60000, 6, 10, 15, ring), W.random_sparse(rng, 3, 6, 10, 15, ring))
+             for _ in range(5)]
+    pairs.append((W.random_sparse(rng, 700, 6, 10, 15, ring), W.random_sparse(rng, 900, 6, 10, 15, ring)))
+    print(f"[batch] large operand keys ring={ring}", flush=True)
+    res = pm.mul_batch((6, 10, ring), [pm.to_device(f) for f, _ in pairs], [pm.to_device(g) for _, g in pairs])
+    assert pm.last_call_status() == 0
+    check_results(pairs, res, ring)
+
+
 def test_batch_with_dense_and_sparse_members():
     pm = _pm()
     # (1+x+y+z+t+u)^10 times itself plus one takes the degree-box path; the
