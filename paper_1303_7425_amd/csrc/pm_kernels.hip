@@ -411,24 +411,29 @@ __global__ __launch_bounds__(NTHREADS) void k_seg_prepare(Ctx C) {
 // position, SM_INDEX (later passes) reads x from the staging buffer.
 enum { SM_STAGED = 0, SM_GEN = 1, SM_INDEX = 2 };
 
-// Digit counts (digit `pass`) of one sort block, two partitions per step so
-// that their loads are in flight together.  Writes the block's histogram,
-// adds it into its range's counter of this pass's parity, and clears the
-// other parity's row of the range for the next pass (the first block of each
-// range does).  Staged keys and pair indices: each thread takes IPT
-// consecutive items (16-byte loads; products start on 64-item boundaries)
-// and counts runs of equal digits in a register, so the LDS sees one add per
-// run: after the low digits are sorted, neighbouring keys mostly share their
-// high digits, and per-item adds would collide in LDS.  Regenerated keys
-// read the product's compressed operand keys (f's then g's, contiguous) from
-// a copy in LDS when they fit in `lds_ck` entries (the dynamic LDS size),
-// else from global memory: LDS serves a 64-lane gather in a few cycles, the
-// vector cache about one line per cycle.  Generated pair indices run along
-// the lanes, so that the LDS reads of g's keys hit distinct banks.
+// Digit counts (digit `pass`) of one sort block by CNT_T threads: CNT_G
+// groups of NTHREADS, each counting its own partitions of the block into its
+// own LDS histogram, so that CNT_G partitions' loads are in flight together.
+// Writes the block's histogram, adds it into its range's counter of this
+// pass's parity, and clears the other parity's row of the range for the next
+// pass (the first block of each range does).  Staged keys and pair indices:
+// each thread takes IPT consecutive items (16-byte loads; products start on
+// 64-item boundaries) and counts runs of equal digits in a register, so the
+// LDS sees one add per run: after the low digits are sorted, neighbouring
+// keys mostly share their high digits, and per-item adds would collide in
+// LDS.  Regenerated keys read the product's compressed operand keys (f's
+// then g's, contiguous) from a copy in LDS when they fit in `lds_ck` entries
+// (the dynamic LDS size), else from global memory: LDS serves a 64-lane
+// gather in a few cycles, the vector cache about one line per cycle.
+// Generated pair indices run along the lanes, so that the LDS reads of g's
+// keys hit distinct banks.
+constexpr int CNT_G = 2;
+constexpr int CNT_T = CNT_G * NTHREADS;
+
 template <typename K, int SM>
-__global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__restrict__ kin,
-                                                    const u32 *__restrict__ xin, int lds_ck) {
-    __shared__ u32 s_h[RADIX];
+__global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void k_count(Ctx C, int pass, const K *__restrict__ kin,
+                                                 const u32 *__restrict__ xin, int lds_ck) {
+    __shared__ u32 s_h[CNT_G][RADIX];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     K *s_ck = (K *)s_dyn;
     const int shift = pass * RADIX_BITS;
@@ -436,12 +441,13 @@ __global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__
     u64 *rz = C.rtot + (i64)((pass + 1) & 1) * C.nrng * RADIX;
     const K *ck = (const K *)C.ck;
     const i64 nblk = C.chpre[C.nseg];
-    const int tid = (int)threadIdx.x;
+    const int grp = (int)threadIdx.x / NTHREADS;
+    const int tid = (int)threadIdx.x % NTHREADS;
     int cur_q = -1;
     OsSeg sq{};
     bool in_lds = false;
     for (i64 b = blockIdx.x; b < nblk; b += gridDim.x) {
-        s_h[tid] = 0;  // RADIX == NTHREADS
+        s_h[grp][tid] = 0;  // RADIX == NTHREADS
         const int q = seg_search(C.chpre, C.nseg, b);
         if (q != cur_q) {
             sq = load_os_seg(C, q);
@@ -451,7 +457,7 @@ __global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__
                 in_lds = m <= lds_ck;
                 if (in_lds) {
                     __syncthreads();  // the previous product's copy is no longer read
-                    for (i64 t = tid; t < m; t += NTHREADS) s_ck[t] = ck[sq.ck_f + t];
+                    for (i64 t = threadIdx.x; t < m; t += CNT_T) s_ck[t] = ck[sq.ck_f + t];
                 }
             }
         }
@@ -461,87 +467,99 @@ __global__ __launch_bounds__(NTHREADS) void k_count(Ctx C, int pass, const K *__
         const i64 p1 = min(sq.first + (sq.n_q + PART - 1) / PART, p0 + C.pblk);
         const K *kf = in_lds ? s_ck : ck + sq.ck_f;
         const K *kg = kf + (sq.ck_g - sq.ck_f);
-        if (bl % RNG == 0) rz[r * RADIX + tid] = 0;
+        if (grp == 0 && bl % RNG == 0) rz[r * RADIX + tid] = 0;
         __syncthreads();
-        for (i64 p = p0; p < p1; p += 2) {
-            K key[2][IPT];
-            int nv[2];
+        for (i64 p = p0 + grp; p < p1; p += CNT_G) {
+            const i64 c = p - sq.first;
+            const int n = (int)min((i64)PART, sq.n_q - c * PART);
             if constexpr (SM == SM_GEN) {
+                // items tid + k * NTHREADS below n, in two halves (registers)
+                u32 prev = 0, cnt = 0;
+#pragma unroll 1
+                for (int h = 0; h < IPT; h += IPT / 2) {
+                    K key[IPT / 2];
 #pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const i64 c = p + h - sq.first;
-                    const int n = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
-                    nv[h] = n;  // items tid + k * NTHREADS below n are valid
-#pragma unroll
-                    for (int k = 0; k < IPT; k++) {
-                        const int idx = tid + k * NTHREADS;
+                    for (int k = 0; k < IPT / 2; k++) {
+                        const int idx = tid + (h + k) * NTHREADS;
                         const u32 x = (u32)(c * PART + idx);
                         const u32 i = div32(x, sq.nb_div);
-                        key[h][k] = idx < n ? kf[i] + kg[x - i * sq.nb] : (K)0;
+                        key[k] = idx < n ? kf[i] + kg[x - i * sq.nb] : (K)0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < IPT / 2; k++) {
+                        const u32 dk = (u32)(key[k] >> shift) & (RADIX - 1);
+                        if (tid + (h + k) * NTHREADS < n) {
+                            if (cnt && dk != prev) {
+                                atomicAdd(&s_h[grp][prev], cnt);
+                                cnt = 0;
+                            }
+                            prev = dk;
+                            cnt++;
+                        }
                     }
                 }
-            } else {
+                if (cnt) atomicAdd(&s_h[grp][prev], cnt);
+                continue;
+            }
+            K key[IPT];
+            int nv;
+            {
+                nv = min(max(n - tid * IPT, 0), IPT);
+                const i64 at = sq.lo + c * PART + (i64)tid * IPT;
+                if constexpr (SM == SM_INDEX) {
+                    u32 x[IPT];
+                    if (nv == IPT) {
 #pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const i64 c = p + h - sq.first;
-                    const int n = p + h < p1 ? (int)min((i64)PART, sq.n_q - c * PART) : 0;
-                    nv[h] = min(max(n - tid * IPT, 0), IPT);
-                    const i64 at = sq.lo + c * PART + (i64)tid * IPT;
-                    if constexpr (SM == SM_INDEX) {
-                        u32 x[IPT];
-                        if (nv[h] == IPT) {
-#pragma unroll
-                            for (int k = 0; k < IPT; k += 4) {
-                                const uint4 w = *(const uint4 *)(xin + at + k);
-                                __builtin_memcpy(&x[k], &w, 16);
-                            }
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < IPT; k++) x[k] = k < nv[h] ? xin[at + k] : 0u;
-                        }
-#pragma unroll
-                        for (int k = 0; k < IPT; k++) {
-                            const u32 i = div32(x[k], sq.nb_div);
-                            key[h][k] = k < nv[h] ? kf[i] + kg[x[k] - i * sq.nb] : (K)0;
+                        for (int k = 0; k < IPT; k += 4) {
+                            const uint4 w = *(const uint4 *)(xin + at + k);
+                            __builtin_memcpy(&x[k], &w, 16);
                         }
                     } else {
-                        constexpr int VW = 16 / (int)sizeof(K);
-                        if (nv[h] == IPT) {
 #pragma unroll
-                            for (int k = 0; k < IPT; k += VW) {
-                                const uint4 w = *(const uint4 *)(kin + at + k);
-                                __builtin_memcpy(&key[h][k], &w, 16);
-                            }
-                        } else {
+                        for (int k = 0; k < IPT; k++) x[k] = k < nv ? xin[at + k] : 0u;
+                    }
 #pragma unroll
-                            for (int k = 0; k < IPT; k++) key[h][k] = k < nv[h] ? kin[at + k] : (K)0;
+                    for (int k = 0; k < IPT; k++) {
+                        const u32 i = div32(x[k], sq.nb_div);
+                        key[k] = k < nv ? kf[i] + kg[x[k] - i * sq.nb] : (K)0;
+                    }
+                } else {
+                    constexpr int VW = 16 / (int)sizeof(K);
+                    if (nv == IPT) {
+#pragma unroll
+                        for (int k = 0; k < IPT; k += VW) {
+                            const uint4 w = *(const uint4 *)(kin + at + k);
+                            __builtin_memcpy(&key[k], &w, 16);
                         }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < IPT; k++) key[k] = k < nv ? kin[at + k] : (K)0;
                     }
                 }
             }
+            u32 prev = (u32)(key[0] >> shift) & (RADIX - 1), cnt = 0;
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                u32 prev = (u32)(key[h][0] >> shift) & (RADIX - 1), cnt = 0;
-#pragma unroll
-                for (int k = 0; k < IPT; k++) {
-                    const u32 dk = (u32)(key[h][k] >> shift) & (RADIX - 1);
-                    const bool valid = SM == SM_GEN ? tid + k * NTHREADS < nv[h] : k < nv[h];
-                    if (valid) {
-                        if (dk != prev) {
-                            atomicAdd(&s_h[prev], cnt);
-                            prev = dk;
-                            cnt = 0;
-                        }
-                        cnt++;
+            for (int k = 0; k < IPT; k++) {
+                const u32 dk = (u32)(key[k] >> shift) & (RADIX - 1);
+                if (k < nv) {
+                    if (dk != prev) {
+                        atomicAdd(&s_h[grp][prev], cnt);
+                        prev = dk;
+                        cnt = 0;
                     }
+                    cnt++;
                 }
-                if (cnt) atomicAdd(&s_h[prev], cnt);
             }
+            if (cnt) atomicAdd(&s_h[grp][prev], cnt);
         }
         __syncthreads();
-        const u32 v = s_h[tid];
-        C.ctot[b * RADIX + tid] = v;
-        if (v) atomicAdd((unsigned long long *)&rt[r * RADIX + tid], (unsigned long long)v);
+        if (grp == 0) {
+            u32 v = 0;
+#pragma unroll
+            for (int g2 = 0; g2 < CNT_G; g2++) v += s_h[g2][tid];
+            C.ctot[b * RADIX + tid] = v;
+            if (v) atomicAdd((unsigned long long *)&rt[r * RADIX + tid], (unsigned long long)v);
+        }
         __syncthreads();
     }
 }
@@ -1557,11 +1575,11 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
             if constexpr (sizeof(V) == 4) {  // SEG_RAW: pair indices
                 const int lds_ck = (int)P.ck_lds;
                 const size_t dyn = (size_t)lds_ck * sizeof(K);
-                if (gen) hipLaunchKernelGGL((k_count<K, SM_GEN>), dim3(nblk_bound), dim3(NTHREADS), dyn, st, C, 0, ka, (const u32 *)va, lds_ck);
-                else if (ix) hipLaunchKernelGGL((k_count<K, SM_INDEX>), dim3(nblk_bound), dim3(NTHREADS), dyn, st, C, pass, ka, (const u32 *)va, lds_ck);
-                else hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
+                if (gen) hipLaunchKernelGGL((k_count<K, SM_GEN>), dim3(nblk_bound), dim3(CNT_T), dyn, st, C, 0, ka, (const u32 *)va, lds_ck);
+                else if (ix) hipLaunchKernelGGL((k_count<K, SM_INDEX>), dim3(nblk_bound), dim3(CNT_T), dyn, st, C, pass, ka, (const u32 *)va, lds_ck);
+                else hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(CNT_T), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
             } else {
-                hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(NTHREADS), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
+                hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(CNT_T), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
             }
             if (P.rscan) hipLaunchKernelGGL(k_range_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C, pass);
         }
