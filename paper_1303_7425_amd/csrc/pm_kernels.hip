@@ -22,6 +22,8 @@
 // paper (problem statement, Fig. 1, Algorithm 1).  The paper's own GPU kernel
 // builds a per-interval 16-ary tree with atomics (Section 6.3); here the merge
 // and sort step is redesigned for CDNA4 as LDS combine + global radix sort.
+#include <type_traits>
+
 #include "pm_internal.hpp"
 
 namespace pm {
@@ -422,17 +424,16 @@ enum { SM_STAGED = 0, SM_GEN = 1, SM_INDEX = 2 };
 // LDS sees one add per run: after the low digits are sorted, neighbouring
 // keys mostly share their high digits, and per-item adds would collide in
 // LDS.  Regenerated keys read the product's compressed operand keys (f's
-// then g's, contiguous) from a copy in LDS when they fit in `lds_ck` entries
-// (the dynamic LDS size), else from global memory: LDS serves a 64-lane
-// gather in a few cycles, the vector cache about one line per cycle.
-// Generated pair indices run along the lanes, so that the LDS reads of g's
-// keys hit distinct banks.
+// then g's, contiguous) from a copy in dynamic LDS (KL: every product of the
+// launch fits), else from global memory: LDS serves a 64-lane gather in a
+// few cycles, the vector cache about one line per cycle.  Generated pair indices run along the
+// lanes, so that the LDS reads of g's keys hit distinct banks.
 constexpr int CNT_G = 2;
 constexpr int CNT_T = CNT_G * NTHREADS;
 
-template <typename K, int SM>
+template <typename K, int SM, bool KL>
 __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void k_count(Ctx C, int pass, const K *__restrict__ kin,
-                                                 const u32 *__restrict__ xin, int lds_ck) {
+                                                 const u32 *__restrict__ xin) {
     __shared__ u32 s_h[CNT_G][RADIX];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     K *s_ck = (K *)s_dyn;
@@ -445,27 +446,23 @@ __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void
     const int tid = (int)threadIdx.x % NTHREADS;
     int cur_q = -1;
     OsSeg sq{};
-    bool in_lds = false;
     for (i64 b = blockIdx.x; b < nblk; b += gridDim.x) {
         s_h[grp][tid] = 0;  // RADIX == NTHREADS
         const int q = seg_search(C.chpre, C.nseg, b);
         if (q != cur_q) {
             sq = load_os_seg(C, q);
             cur_q = q;
-            if constexpr (SM != SM_STAGED) {
+            if constexpr (KL) {
                 const i64 m = sq.ck_g - sq.ck_f + sq.nb;  // f's and g's compressed keys
-                in_lds = m <= lds_ck;
-                if (in_lds) {
-                    __syncthreads();  // the previous product's copy is no longer read
-                    for (i64 t = threadIdx.x; t < m; t += CNT_T) s_ck[t] = ck[sq.ck_f + t];
-                }
+                __syncthreads();  // the previous product's copy is no longer read
+                for (i64 t = threadIdx.x; t < m; t += CNT_T) s_ck[t] = ck[sq.ck_f + t];
             }
         }
         const i64 bl = b - C.chpre[q];
         const i64 r = C.rpre[q] + bl / RNG;
         const i64 p0 = sq.first + bl * C.pblk;
         const i64 p1 = min(sq.first + (sq.n_q + PART - 1) / PART, p0 + C.pblk);
-        const K *kf = in_lds ? s_ck : ck + sq.ck_f;
+        const K *kf = KL ? s_ck : ck + sq.ck_f;
         const K *kg = kf + (sq.ck_g - sq.ck_f);
         if (grp == 0 && bl % RNG == 0) rz[r * RADIX + tid] = 0;
         __syncthreads();
@@ -652,11 +649,17 @@ __device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 sta
 constexpr int OS_T = 512;            // radix-pass workgroup: 8 waves
 constexpr int OS_IPT = PART / OS_T;  // items per thread
 
-template <typename K, typename V>
+// DG: the pass keeps each item's digit rather than its key in LDS (passes of
+// regenerated keys that do not write keys), which leaves LDS room for a copy
+// of the operands' compressed keys.
+template <typename K, typename V, bool DG = false>
 struct OsSmem {
     static constexpr int NW = OS_T / 64;
-    static constexpr int OCC = os_resident((int)sizeof(K), (int)sizeof(V)) * OS_T / 256;  // waves per SIMD
-    K k[PART];
+    // waves per SIMD the registers are held to (with the LDS copy of the
+    // operand keys, two workgroups per CU)
+    static constexpr int OCC = (DG ? 2 : os_resident((int)sizeof(K), (int)sizeof(V))) * OS_T / 256;
+    using KS = std::conditional_t<DG, unsigned char, K>;
+    KS k[PART];
     V v[PART];
     u32 wh[NW][RADIX];
     u32 loff[RADIX];
@@ -672,7 +675,8 @@ struct OsSmem {
 // only that digit's count and the global writes account for them.
 template <typename K, typename V, int SM>
 __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int n, const K *__restrict__ kin,
-                                        const V *__restrict__ vin, K (&key)[OS_IPT], V (&val)[OS_IPT]) {
+                                        const V *__restrict__ vin, const K *kf, const K *kg, K (&key)[OS_IPT],
+                                        V (&val)[OS_IPT]) {
     // an opaque copy of the thread index: keeps the per-item index and
     // address arithmetic here instead of holding sixteen of each in
     // registers for the whole kernel
@@ -680,13 +684,14 @@ __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int
     asm volatile("" : "+v"(tid));
     const int wbase = (tid >> 6) * 64 * OS_IPT + (tid & 63);
     const i64 start = s.lo + c * PART;
-    const K *ckeys = (const K *)C.ck;
+    // kf, kg: f's and g's compressed keys (an LDS copy or global memory)
     if constexpr (SM == SM_GEN) {
 #pragma unroll
         for (int k = 0; k < OS_IPT; k++) {
             const int idx = wbase + k * 64;
             const u32 x = (u32)(c * PART + idx);
-            key[k] = idx < n ? raw_key_os<K>(s, ckeys, x) : ~(K)0;
+            const u32 i = div32(x, s.nb_div);
+            key[k] = idx < n ? kf[i] + kg[x - i * s.nb] : ~(K)0;
             val[k] = (V)x;
         }
     } else if constexpr (SM == SM_INDEX) {
@@ -698,7 +703,8 @@ __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int
 #pragma unroll
         for (int k = 0; k < OS_IPT; k++) {
             const int idx = wbase + k * 64;
-            key[k] = idx < n ? raw_key_os<K>(s, ckeys, (u32)val[k]) : ~(K)0;
+            const u32 i = div32((u32)val[k], s.nb_div);
+            key[k] = idx < n ? kf[i] + kg[(u32)val[k] - i * s.nb] : ~(K)0;
         }
     } else {
 #pragma unroll
@@ -720,12 +726,13 @@ __device__ __forceinline__ void os_load(const Ctx &C, const OsSeg &s, i64 c, int
 // loads the next partition (cn, nn items; nn = 0: none) into key/val.  `run`
 // (thread d) is digit d's next position in the staging buffer.  Expects the
 // wave digit counters S.wh zeroed and leaves them zeroed.
-template <typename K, typename V, int SM, bool WK>
-__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSeg &s, int pass, int n, i64 cn,
+template <typename K, typename V, int SM, bool WK, bool DG>
+__device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const OsSeg &s, int pass, int n, i64 cn,
                                              int nn, const K *__restrict__ kin, const V *__restrict__ vin,
                                              K *__restrict__ kout, V *__restrict__ vout, K (&key)[OS_IPT],
-                                             V (&val)[OS_IPT], u64 &run) {
-    constexpr int NW = OsSmem<K, V>::NW;
+                                             V (&val)[OS_IPT], u64 &run, const K *kf, const K *kg) {
+    constexpr int NW = OsSmem<K, V, DG>::NW;
+    using KS = typename OsSmem<K, V, DG>::KS;
     const int shift = pass * RADIX_BITS;
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
@@ -790,11 +797,11 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     for (int k = 0; k < OS_IPT; k++) {
         const u32 dk = (u32)((key[k] >> shift) & (RADIX - 1));
         const u32 pos = S.loff[dk] + S.wh[w][dk] + rk[k];
-        S.k[pos] = key[k];
+        S.k[pos] = DG ? (KS)dk : (KS)key[k];
         S.v[pos] = val[k];
     }
     __syncthreads();
-    if (nn > 0) os_load<K, V, SM>(C, s, cn, nn, kin, vin, key, val);
+    if (nn > 0) os_load<K, V, SM>(C, s, cn, nn, kin, vin, kf, kg, key, val);
 #pragma unroll
     for (int e = 0; e < NW * RADIX / OS_T; e++) (&S.wh[0][0])[tid + e * OS_T] = 0;
     // sorted item i of digit d goes to goff[d] + i; a position outside the
@@ -808,9 +815,9 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
 #pragma unroll
         for (int k = 0; k < OS_IPT; k++) {
             const u32 i = (u32)tid + (u32)(k * OS_T);
-            const K kv = S.k[i];
+            const KS kv = S.k[i];
             const V vv = S.v[i];
-            u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
+            u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & (RADIX - 1)] + i;
             bad |= rel >= span32;
             rel = min(rel, span32 - 1u);
             if constexpr (WK) kq[rel] = kv;
@@ -821,8 +828,8 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
         for (int k = 0; k < OS_IPT; k++) {
             const u32 i = (u32)tid + (u32)(k * OS_T);
             if (i < (u32)n) {
-                const K kv = S.k[i];
-                const u32 rel = S.goff[(u32)(kv >> shift) & (RADIX - 1)] + i;
+                const KS kv = S.k[i];
+                const u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & (RADIX - 1)] + i;
                 if (rel < span32) {
                     if constexpr (WK) kq[rel] = kv;
                     vq[rel] = S.v[i];
@@ -836,16 +843,24 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V> &S, const OsSe
     __syncthreads();
 }
 
-template <typename K, typename V, int SM, bool WK>
-__global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
+// KL: regenerated keys read each product's compressed operand keys from a
+// copy in dynamic LDS (every product of the launch fits; DG passes only),
+// else from global memory.
+template <typename K, typename V, int SM, bool WK, bool KL>
+__global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V, KL && SM != SM_STAGED && !WK>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
-    constexpr int NW = OsSmem<K, V>::NW;
-    __shared__ OsSmem<K, V> S;
+    constexpr bool DG = KL && SM != SM_STAGED && !WK;
+    constexpr int NW = OsSmem<K, V, DG>::NW;
+    __shared__ OsSmem<K, V, DG> S;
     __shared__ i64 s_b;
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    K *s_ck = (K *)s_dyn;
+    const K *ck = (const K *)C.ck;
     const i64 nblk = C.chpre[C.nseg];
     int cur_q = -1;
     OsSeg sq{};
+    const K *kf = nullptr, *kg = nullptr;
     for (int e = threadIdx.x; e < NW * RADIX; e += OS_T) (&S.wh[0][0])[e] = 0;
     K key[OS_IPT];
     V val[OS_IPT];
@@ -860,16 +875,24 @@ __global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, 
         if (q != cur_q) {
             sq = load_os_seg(C, q);
             cur_q = q;
+            kf = ck + sq.ck_f;
+            if constexpr (KL) {  // the previous block ended with a barrier
+                const i64 m = sq.ck_g - sq.ck_f + sq.nb;  // f's and g's compressed keys, contiguous
+                for (i64 t = threadIdx.x; t < m; t += OS_T) s_ck[t] = kf[t];
+                kf = s_ck;
+                __syncthreads();
+            }
+            kg = kf + (sq.ck_g - sq.ck_f);
         }
         const i64 bl = b - C.chpre[q];
         const i64 c0 = bl * C.pblk;
         const i64 c1 = min((sq.n_q + PART - 1) / PART, c0 + C.pblk);
-        os_load<K, V, SM>(C, sq, c0, (int)min((i64)PART, sq.n_q - c0 * PART), kin, vin, key, val);
+        os_load<K, V, SM>(C, sq, c0, (int)min((i64)PART, sq.n_q - c0 * PART), kin, vin, kf, kg, key, val);
         u64 run = block_start<OS_T>(C, pass, q, bl, (u64)sq.lo, S.scan64);
         for (i64 c = c0; c < c1; c++) {
             const int n = (int)min((i64)PART, sq.n_q - c * PART);
             const int nn = c + 1 < c1 ? (int)min((i64)PART, sq.n_q - (c + 1) * PART) : 0;
-            os_partition<K, V, SM, WK>(C, S, sq, pass, n, c + 1, nn, kin, vin, kout, vout, key, val, run);
+            os_partition<K, V, SM, WK, DG>(C, S, sq, pass, n, c + 1, nn, kin, vin, kout, vout, key, val, run, kf, kg);
         }
     }
 }
@@ -1573,13 +1596,15 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         {
             ProfScope ps("count", st);
             if constexpr (sizeof(V) == 4) {  // SEG_RAW: pair indices
-                const int lds_ck = (int)P.ck_lds;
-                const size_t dyn = (size_t)lds_ck * sizeof(K);
-                if (gen) hipLaunchKernelGGL((k_count<K, SM_GEN>), dim3(nblk_bound), dim3(CNT_T), dyn, st, C, 0, ka, (const u32 *)va, lds_ck);
-                else if (ix) hipLaunchKernelGGL((k_count<K, SM_INDEX>), dim3(nblk_bound), dim3(CNT_T), dyn, st, C, pass, ka, (const u32 *)va, lds_ck);
-                else hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(CNT_T), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
+                // every product's operand keys fit the LDS copy (P.ck_fit)
+                const size_t dyn = (size_t)P.ck_lds * sizeof(K);
+                const u32 *xa = (const u32 *)va;
+                if (gen && P.ck_fit) hipLaunchKernelGGL((k_count<K, SM_GEN, true>), dim3(nblk_bound), dim3(CNT_T), dyn, st, C, 0, ka, xa);
+                else if (gen) hipLaunchKernelGGL((k_count<K, SM_GEN, false>), dim3(nblk_bound), dim3(CNT_T), 0, st, C, 0, ka, xa);
+                else if (ix) hipLaunchKernelGGL((k_count<K, SM_INDEX, true>), dim3(nblk_bound), dim3(CNT_T), dyn, st, C, pass, ka, xa);
+                else hipLaunchKernelGGL((k_count<K, SM_STAGED, false>), dim3(nblk_bound), dim3(CNT_T), 0, st, C, pass, ka, xa);
             } else {
-                hipLaunchKernelGGL((k_count<K, SM_STAGED>), dim3(nblk_bound), dim3(CNT_T), 0, st, C, pass, ka, (const u32 *)nullptr, 0);
+                hipLaunchKernelGGL((k_count<K, SM_STAGED, false>), dim3(nblk_bound), dim3(CNT_T), 0, st, C, pass, ka, (const u32 *)nullptr);
             }
             if (P.rscan) hipLaunchKernelGGL(k_range_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C, pass);
         }
@@ -1587,13 +1612,21 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         // and the last pass of a pair-index sort (it also writes the keys)
         ProfScope ps(gen ? "onesweep_gen" : (ix && last) ? "onesweep_last" : "onesweep", st);
         if constexpr (sizeof(V) == 4) {
-            if (gen && (last || !ix)) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
-            else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
-            else if (!ix) hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
-            else if (last) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, true>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
-            else hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+            // passes that keep digits in LDS hold the operand keys there too
+            // when two workgroups per CU still fit
+            constexpr size_t os_static = sizeof(OsSmem<K, V, true>) + 256;
+            const bool kl = 2 * (os_static + (size_t)P.ck_lds * sizeof(K)) <= (size_t)160 << 10;
+            const size_t dyn = (size_t)P.ck_lds * sizeof(K);
+            const dim3 gd(std::min(g, cus * 2));
+            if (gen && (last || !ix)) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+            else if (gen && kl) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false, true>), gd, dim3(OS_T), dyn, st, C, 0, ka, va, kb, vb);
+            else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+            else if (!ix) hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+            else if (last) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, true, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+            else if (kl) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false, true>), gd, dim3(OS_T), dyn, st, C, pass, ka, va, kb, vb);
+            else hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
         } else {
-            hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+            hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
         }
         std::swap(ka, kb);
         std::swap(va, vb);

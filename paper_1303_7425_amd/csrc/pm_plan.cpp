@@ -293,14 +293,16 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     // them in one launch, as in large batches, or a product with more than
     // 64 KB of them) the generating pass writes the keys and later passes
     // carry them.
-    P.ix = (int64_t)nck * P.ksize <= (int64_t)1 << 20;
+    P.ck_fit = 1;
     P.ck_lds = 0;
     for (int q = 0; q < S; q++) {
         const int64_t m = P.segs[q].na + P.segs[q].nb;
         if (P.segs[q].mode != SEG_RAW) continue;
         if (m * P.ksize <= (64 << 10)) P.ck_lds = std::max<int64_t>(P.ck_lds, m);
-        else P.ix = 0;
+        else P.ck_fit = 0;
     }
+    if (!P.ck_fit) P.ck_lds = 0;
+    P.ix = P.ck_fit && (int64_t)nck * P.ksize <= (int64_t)1 << 20;
 
     // workspace layout
     size_t off = 0;

@@ -80,6 +80,7 @@ struct Plan {
     size_t o_pcnt = 0, o_ctot = 0, o_rtot = 0, o_chpre = 0, o_rpre = 0, o_pbase = 0;
     int64_t ck_lds = 0;       // compressed operand keys a digit-count workgroup copies to LDS (entries)
     int ix = 1;               // pair-index sorts regenerate keys in every pass (else carry them)
+    int ck_fit = 0;           // every pair-index product's compressed operand keys fit ck_lds
     int64_t nrng = 1;         // range rows of the radix-pass counters
     int rscan = 0;            // some product may have more than RSUM_MAX ranges
     size_t total = 0;
