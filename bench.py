@@ -40,11 +40,15 @@ def measured_traffic(label):
 
 # rocprofv3 kernel names -> the labels used in the summaries
 KERNEL_LABELS = [
-    ("k_onesweep<unsigned int, unsigned int, 2, false>", "onesweep pass (pair indices)"),
-    ("k_onesweep<unsigned int, unsigned int, 2, true>", "onesweep last pass (pair indices, writes keys)"),
-    ("k_onesweep<unsigned int, unsigned int, 1, false>", "onesweep pass 0 (generates pair indices)"),
-    ("k_count<unsigned int, 2>", "count (pair indices)"),
-    ("k_count<unsigned int, 1>", "count (generated pair indices)"),
+    ("k_onesweep<unsigned int, unsigned int, 2, false, true>", "onesweep pass (pair indices)"),
+    ("k_onesweep<unsigned int, unsigned int, 2, false, false>", "onesweep pass (pair indices, keys via cache)"),
+    ("k_onesweep<unsigned int, unsigned int, 2, true, false>", "onesweep last pass (pair indices, writes keys)"),
+    ("k_onesweep<unsigned int, unsigned int, 1, false, true>", "onesweep pass 0 (generates pair indices)"),
+    ("k_onesweep<unsigned int, unsigned int, 1, true, false>", "onesweep pass 0 (generates, writes keys)"),
+    ("k_onesweep<unsigned int, unsigned int, 0, true, false>", "onesweep pass (keys and pair indices)"),
+    ("k_count<unsigned int, 2,", "count (pair indices)"),
+    ("k_count<unsigned int, 1,", "count (generated pair indices)"),
+    ("k_count<unsigned int, 0,", "count (staged keys)"),
     ("k_range_scan", "range_scan"),
     ("k_head_count<", "head_count"),
     ("k_head_scan", "head_scan"),
