@@ -104,6 +104,16 @@ def test_random_6var_ragged(ring, na, nb):
     check(f, g, f"rand {na}x{nb}")
 
 
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_operand_keys_beyond_radix_lds_copy(ring):
+    """14,000 operand terms (56 KB of compressed keys): the digit counts copy
+    them to LDS, the radix passes regenerate keys through the vector cache."""
+    rng = W.rng_for(91)
+    f = W.random_sparse(rng, 13000, 6, 10, 15, ring)
+    g = W.random_sparse(rng, 1000, 6, 10, 15, ring)
+    check(f, g, f"keys beyond radix LDS ({ring})")
+
+
 @pytest.mark.parametrize("mode", ["auto", "pairs", "combine", "intervals", "nodense", "nodense_combine",
                                   "nodense_intervals", "tile1", "tile2"])
 def test_tuning_modes_same_result(mode):
