@@ -1037,6 +1037,7 @@ __global__ __launch_bounds__(RED_T) __attribute__((amdgpu_waves_per_eu(sizeof(K)
     __shared__ u64 s_v[PADN];
     __shared__ u32 s_scan[RED_T / 64];
     __shared__ int s_wp[RED_T / 64];
+    __shared__ int s_cont;
     __shared__ u64 s_ws[RED_T / 64];
     __shared__ i64 s_p, s_pn;
     __shared__ u64 s_base;
@@ -1060,7 +1061,10 @@ __global__ __launch_bounds__(RED_T) __attribute__((amdgpu_waves_per_eu(sizeof(K)
         const i64 start = s.lo + c * PART;
         const i64 send = s.lo + n_q;
         const int n = (int)min((i64)PART, n_q - c * PART);
-        if (threadIdx.x == 0) s_z = 0;
+        if (threadIdx.x == 0) {
+            s_z = 0;
+            s_cont = -1;
+        }
         // opaque thread index: per-item index arithmetic stays in the loop
         int tid = (int)threadIdx.x;
         asm volatile("" : "+v"(tid));
@@ -1149,11 +1153,8 @@ __global__ __launch_bounds__(RED_T) __attribute__((amdgpu_waves_per_eu(sizeof(K)
                     const K key = s_k[pad(b0 + open)];
                     int j = b0 + RED_IPT;
                     while (j < n && s_k[pad(j)] == key) acc = ring_add<RING>(acc, s_v[pad(j++)]);
-                    if (j >= n && n > 0) {
-                        for (i64 g = start + n; g < send && kin[g] == key; g++)
-                            acc = ring_add<RING>(acc, item_value_rd<K, V, RING>(s, vin[g]));
-                    }
                     s_v[pad(b0 + open)] = acc;
+                    if (j >= n && n > 0) s_cont = b0 + open;  // continues past the partition
                 }
             }
         } else {
@@ -1229,16 +1230,35 @@ __global__ __launch_bounds__(RED_T) __attribute__((amdgpu_waves_per_eu(sizeof(K)
                 int fp = lp >= 0 ? lp : cp;
                 u64 fs = lp >= 0 ? ls : ring_add<RING>(cs, pre);
                 if (fp >= 0) {
-                    const K key = s_k[pad(fp)];
-                    for (i64 g = start + n; g < send && kin[g] == key; g++)
-                        fs = ring_add<RING>(fs, item_value_rd<K, V, RING>(s, vin[g]));
                     s_v[pad(fp)] = fs;
+                    s_cont = fp;  // may continue past the partition
                 }
             }
             // a run still open at this thread's end is completed by the thread
             // holding the next head or the partition's last item
             __syncthreads();
         }
+        // the partition's last run may continue into the next partitions: wave 0
+        // reads 64 items at a time and adds the matching prefix (left to right)
+        if constexpr (RING == RING_F64) __syncthreads();
+        if (tid < 64) {
+            const int cp = s_cont;
+            if (cp >= 0) {
+                const K key = s_k[pad(cp)];
+                u64 acc = s_v[pad(cp)];
+                for (i64 g = start + n; g < send; g += 64) {
+                    const i64 gi = g + tid;
+                    const bool m = gi < send && kin[gi] == key;
+                    const u64 mb = __ballot(m);
+                    const int cnt = mb == ~0ull ? 64 : __builtin_ctzll(~mb);
+                    const u64 v = tid < cnt ? item_value_rd<K, V, RING>(s, vin[gi]) : 0;
+                    for (int t = 0; t < cnt; t++) acc = ring_add<RING>(acc, __shfl(v, t, 64));
+                    if (cnt < 64) break;
+                }
+                if (tid == 0) s_v[pad(cp)] = acc;
+            }
+        }
+        __syncthreads();
         u32 tk = 0;
         if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);  // next partition
         // gather this thread's runs, then stage them by slot in LDS
