@@ -31,13 +31,26 @@ constexpr int NTHREADS = 256;          // threads per workgroup (4 wave64s)
 constexpr int IPT = 16;                // items per thread in sort / reduce partitions
 constexpr int PART = NTHREADS * IPT;   // items per partition
 constexpr int RNG = 64;                // sort blocks per range
-constexpr int PBLK_MAX = 16;           // sort partitions per sort block, at most
+constexpr int PBLK_MAX = 32;           // sort partitions per sort block, at most
 constexpr int RSUM_MAX = 16;           // products with at most this many ranges need no range scan
 // Radix-pass workgroups (512 threads) resident per CU: three when keys and
 // payloads are 4 bytes each (LDS and registers allow it), else two.
+constexpr int OS_T = 512;
 constexpr int os_resident(int ksize, int vsize) { return ksize + vsize <= 8 ? 3 : 2; }
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
+
+// LDS bytes of a radix-pass workgroup that keeps each item's digit byte (dg)
+// or its key, its payload, the per-wave digit counters and the digit offsets
+// (an upper bound of the kernel's shared block).
+constexpr size_t os_lds_bytes(int ksize, int vsize, bool dg) {
+    return (size_t)PART * ((dg ? 1 : ksize) + vsize) + (size_t)(OS_T / 64) * RADIX * 4 + 2 * RADIX * 4 + 256;
+}
+// Pair-index radix passes hold a copy of the operands' compressed keys (ck
+// entries) in LDS when two such workgroups still fit a CU's 160 KB.
+constexpr bool os_keys_in_lds(int64_t ck, int ksize, int vsize) {
+    return ck > 0 && 2 * (os_lds_bytes(ksize, vsize, true) + (size_t)ck * ksize) <= ((size_t)160 << 10);
+}
 constexpr int MAX_PASSES = 8;
 constexpr int MAX_VARS = 64;
 

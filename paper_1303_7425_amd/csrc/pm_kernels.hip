@@ -646,12 +646,18 @@ __device__ inline u64 block_start(const Ctx &C, int pass, int q, i64 bl, u64 sta
 // partition's digit count.  WK: the pass also writes the keys (always for
 // staged items; for pair indices only in the last pass, for the reduction).
 // ---------------------------------------------------------------------------
-constexpr int OS_T = 512;            // radix-pass workgroup: 8 waves
-constexpr int OS_IPT = PART / OS_T;  // items per thread
+constexpr int OS_IPT = PART / OS_T;  // items per thread (OS_T = 512: 8 waves)
 
 // DG: the pass keeps each item's digit rather than its key in LDS (passes of
-// regenerated keys that do not write keys), which leaves LDS room for a copy
-// of the operands' compressed keys.
+// regenerated keys; one that writes keys regenerates them again), which
+// leaves LDS room for a copy of the operands' compressed keys.
+
+// The key ck(alpha_i) + ck(beta_j) of pair index x = i*nb + j.
+template <typename K>
+__device__ inline K regen_key(const OsSeg &s, const K *kf, const K *kg, u32 x) {
+    const u32 i = div32(x, s.nb_div);
+    return kf[i] + kg[x - i * s.nb];
+}
 template <typename K, typename V, bool DG = false>
 struct OsSmem {
     static constexpr int NW = OS_T / 64;
@@ -820,7 +826,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
             u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & (RADIX - 1)] + i;
             bad |= rel >= span32;
             rel = min(rel, span32 - 1u);
-            if constexpr (WK) kq[rel] = kv;
+            if constexpr (WK) kq[rel] = DG ? regen_key(s, kf, kg, (u32)vv) : (K)kv;
             vq[rel] = vv;
         }
     } else {
@@ -831,8 +837,9 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
                 const KS kv = S.k[i];
                 const u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & (RADIX - 1)] + i;
                 if (rel < span32) {
-                    if constexpr (WK) kq[rel] = kv;
-                    vq[rel] = S.v[i];
+                    const V vv = S.v[i];
+                    if constexpr (WK) kq[rel] = DG ? regen_key(s, kf, kg, (u32)vv) : (K)kv;
+                    vq[rel] = vv;
                 } else {
                     bad = true;
                 }
@@ -844,13 +851,13 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
 }
 
 // KL: regenerated keys read each product's compressed operand keys from a
-// copy in dynamic LDS (every product of the launch fits; DG passes only),
-// else from global memory.
+// copy in dynamic LDS (every product of the launch fits), else from global
+// memory.
 template <typename K, typename V, int SM, bool WK, bool KL>
-__global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V, KL && SM != SM_STAGED && !WK>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
+__global__ __launch_bounds__(OS_T) __attribute__((amdgpu_waves_per_eu(OsSmem<K, V, KL && SM != SM_STAGED>::OCC))) void k_onesweep(Ctx C, int pass, const K *__restrict__ kin,
                                                         const V *__restrict__ vin, K *__restrict__ kout,
                                                         V *__restrict__ vout) {
-    constexpr bool DG = KL && SM != SM_STAGED && !WK;
+    constexpr bool DG = KL && SM != SM_STAGED;
     constexpr int NW = OsSmem<K, V, DG>::NW;
     __shared__ OsSmem<K, V, DG> S;
     __shared__ i64 s_b;
@@ -1603,7 +1610,7 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         hipLaunchKernelGGL(k_seg_prepare, dim3(1), dim3(NTHREADS), 0, st, C);
     }
     const int nblk_bound = (int)std::min<int64_t>(P.nparts_bound / P.pblk + P.nseg + 1, (int64_t)cus * 16);
-    const int g = std::max(1, std::min(nblk_bound, cus * os_resident((int)sizeof(K), (int)sizeof(V))));
+    const int g = std::max(1, std::min(nblk_bound, cus * (P.kl ? 2 : os_resident((int)sizeof(K), (int)sizeof(V)))));
     K *ka = (K *)C.stA_k, *kb = (K *)C.stB_k;
     V *va = (V *)C.stA_v, *vb = (V *)C.stB_v;
     for (int pass = 0; pass < P.passes; pass++) {
@@ -1632,19 +1639,22 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
         // and the last pass of a pair-index sort (it also writes the keys)
         ProfScope ps(gen ? "onesweep_gen" : (ix && last) ? "onesweep_last" : "onesweep", st);
         if constexpr (sizeof(V) == 4) {
-            // passes that keep digits in LDS hold the operand keys there too
-            // when two workgroups per CU still fit
-            constexpr size_t os_static = sizeof(OsSmem<K, V, true>) + 256;
-            const bool kl = 2 * (os_static + (size_t)P.ck_lds * sizeof(K)) <= (size_t)160 << 10;
-            const size_t dyn = (size_t)P.ck_lds * sizeof(K);
-            const dim3 gd(std::min(g, cus * 2));
-            if (gen && (last || !ix)) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
-            else if (gen && kl) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false, true>), gd, dim3(OS_T), dyn, st, C, 0, ka, va, kb, vb);
-            else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+            // pair-index passes hold the operand keys in LDS (P.kl: two
+            // workgroups per CU, every product fits); the grid g matches
+            const size_t dyn = P.kl ? (size_t)P.ck_lds * sizeof(K) : 0;
+            if (gen && !ix) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
             else if (!ix) hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
-            else if (last) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, true, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
-            else if (kl) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false, true>), gd, dim3(OS_T), dyn, st, C, pass, ka, va, kb, vb);
-            else hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+            else if (P.kl) {
+                if (gen && last) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true, true>), dim3(g), dim3(OS_T), dyn, st, C, 0, ka, va, kb, vb);
+                else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false, true>), dim3(g), dim3(OS_T), dyn, st, C, 0, ka, va, kb, vb);
+                else if (last) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, true, true>), dim3(g), dim3(OS_T), dyn, st, C, pass, ka, va, kb, vb);
+                else hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false, true>), dim3(g), dim3(OS_T), dyn, st, C, pass, ka, va, kb, vb);
+            } else {
+                if (gen && last) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, true, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+                else if (gen) hipLaunchKernelGGL((k_onesweep<K, V, SM_GEN, false, false>), dim3(g), dim3(OS_T), 0, st, C, 0, ka, va, kb, vb);
+                else if (last) hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, true, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+                else hipLaunchKernelGGL((k_onesweep<K, V, SM_INDEX, false, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
+            }
         } else {
             hipLaunchKernelGGL((k_onesweep<K, V, SM_STAGED, true, false>), dim3(g), dim3(OS_T), 0, st, C, pass, ka, va, kb, vb);
         }

@@ -81,6 +81,7 @@ struct Plan {
     int64_t ck_lds = 0;       // compressed operand keys a digit-count workgroup copies to LDS (entries)
     int ix = 1;               // pair-index sorts regenerate keys in every pass (else carry them)
     int ck_fit = 0;           // every pair-index product's compressed operand keys fit ck_lds
+    int kl = 0;               // pair-index radix passes copy the operand keys to LDS (two workgroups per CU)
     int64_t nrng = 1;         // range rows of the radix-pass counters
     int rscan = 0;            // some product may have more than RSUM_MAX ranges
     size_t total = 0;
