@@ -428,7 +428,7 @@ enum { SM_STAGED = 0, SM_GEN = 1, SM_INDEX = 2 };
 // launch fits), else from global memory: LDS serves a 64-lane gather in a
 // few cycles, the vector cache about one line per cycle.  Generated pair indices run along the
 // lanes, so that the LDS reads of g's keys hit distinct banks.
-constexpr int CNT_G = 2;
+constexpr int CNT_G = 3;
 constexpr int CNT_T = CNT_G * NTHREADS;
 
 template <typename K, int SM, bool KL>
