@@ -337,25 +337,21 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     // sort blocks fill the radix passes' resident workgroups
     P.kl = P.raw && P.ix && os_keys_in_lds(P.ck_lds, P.ksize, P.vsize);
     const int64_t resident = (int64_t)cus * (P.kl ? 2 : os_resident(P.ksize, P.vsize));
-    // a workgroup's pass time goes with (blocks it takes) x pblk: choose pblk
-    // so that the blocks fill whole rounds of the resident grid
-    P.pblk = 1;
-    {
-        int64_t best = -1;
-        for (int64_t pb = PBLK_MAX; pb >= 1; pb--) {
-            int64_t nb = 0;
-            for (int q = 0; q < S; q++) {
-                const DevSeg &d = P.segs[q];
-                if (d.mode != SEG_RAW && d.mode != SEG_COMBINE) continue;
-                nb += ((d.stage_bound + PART - 1) / PART + pb - 1) / pb;
-            }
-            const int64_t cost = (nb + resident - 1) / resident * pb;
-            if (best < 0 || cost < best) {
-                best = cost;
-                P.pblk = pb;
-            }
+    // A workgroup's pass time goes with the blocks it takes times pblk: when
+    // some pblk up to PBLK_MAX makes one block per resident workgroup, take
+    // the smallest; otherwise (many rounds, where the ticket queue balances
+    // finer blocks better) blocks of at most 16 partitions.
+    P.pblk = 0;
+    for (int64_t pb = 1; pb <= PBLK_MAX && !P.pblk; pb++) {
+        int64_t nb = 0;
+        for (int q = 0; q < S; q++) {
+            const DevSeg &d = P.segs[q];
+            if (d.mode != SEG_RAW && d.mode != SEG_COMBINE) continue;
+            nb += ((d.stage_bound + PART - 1) / PART + pb - 1) / pb;
         }
+        if (nb <= resident) P.pblk = pb;
     }
+    if (!P.pblk) P.pblk = std::max<int64_t>(1, std::min<int64_t>(16, (P.nparts_bound + resident - 1) / resident));
     // range counters of the radix passes, two sets by pass parity (zeroed here,
     // then each counting kernel clears the other set for the next pass)
     P.nrng = (P.nparts_bound / P.pblk + S + 1) / RNG + S + 1;
