@@ -42,8 +42,10 @@ def measured_traffic(label):
 KERNEL_LABELS = [
     ("k_onesweep<unsigned int, unsigned int, 2, false, true>", "onesweep pass (pair indices)"),
     ("k_onesweep<unsigned int, unsigned int, 2, false, false>", "onesweep pass (pair indices, keys via cache)"),
-    ("k_onesweep<unsigned int, unsigned int, 2, true, false>", "onesweep last pass (pair indices, writes keys)"),
+    ("k_onesweep<unsigned int, unsigned int, 2, true, true>", "onesweep last pass (pair indices, writes keys)"),
+    ("k_onesweep<unsigned int, unsigned int, 2, true, false>", "onesweep last pass (keys via cache)"),
     ("k_onesweep<unsigned int, unsigned int, 1, false, true>", "onesweep pass 0 (generates pair indices)"),
+    ("k_onesweep<unsigned int, unsigned int, 1, true, true>", "onesweep single pass (generates, writes keys)"),
     ("k_onesweep<unsigned int, unsigned int, 1, true, false>", "onesweep pass 0 (generates, writes keys)"),
     ("k_onesweep<unsigned int, unsigned int, 0, true, false>", "onesweep pass (keys and pair indices)"),
     ("k_count<unsigned int, 2,", "count (pair indices)"),
