@@ -33,11 +33,14 @@ namespace pm {
 // the exponents, strict ascending order, key bits outside the fields, and
 // coefficient range.  out[(q*2+side)*2*nvars + v] = min, [... + nvars + v] = max.
 // One sweep over the terms per group of eight variables, four independent
-// loads in flight per thread; the checks ride along with the first group.
+// loads in flight per thread (1024 threads: an operand of a few thousand
+// terms takes one or two steps); the checks ride along with the first group.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NTHREADS) void k_stats(const DevSeg *segs, int nvars, int bits, int ring, u64 *out,
+constexpr int ST_T = 1024;
+
+__global__ __launch_bounds__(ST_T) void k_stats(const DevSeg *segs, int nvars, int bits, int ring, u64 *out,
                                                      u32 *flags) {
-    constexpr int G = 8, U = 4, NW = NTHREADS / 64;
+    constexpr int G = 8, U = 4, NW = ST_T / 64;
     const int q = blockIdx.x >> 1, side = blockIdx.x & 1;
     const DevSeg &s = segs[q];
     const i64 n = side ? s.nb : s.na;
@@ -60,18 +63,18 @@ __global__ __launch_bounds__(NTHREADS) void k_stats(const DevSeg *segs, int nvar
             mx[u] = 0;
             sh[u] = v0 + u < nvars ? (u32)((nvars - 1 - (v0 + u)) * bits) : 0u;
         }
-        for (i64 i0 = threadIdx.x; i0 < n; i0 += U * NTHREADS) {
+        for (i64 i0 = threadIdx.x; i0 < n; i0 += U * ST_T) {
             u64 kk[U], kp[U], cc[U];
 #pragma unroll
             for (int r = 0; r < U; r++) {
-                const i64 i = i0 + (i64)r * NTHREADS;
+                const i64 i = i0 + (i64)r * ST_T;
                 kk[r] = i < n ? k[i] : 0;
                 kp[r] = (v0 == 0 && i > 0 && i < n) ? k[i - 1] : 0;
                 cc[r] = (v0 == 0 && i < n) ? c[i] : 0;
             }
 #pragma unroll
             for (int r = 0; r < U; r++) {
-                const i64 i = i0 + (i64)r * NTHREADS;
+                const i64 i = i0 + (i64)r * ST_T;
                 if (i >= n) continue;
                 if (v0 == 0) {
                     if (used < 64 && (kk[r] >> used) != 0) fl |= ST_BADBITS;
@@ -944,17 +947,19 @@ __global__ __launch_bounds__(NTHREADS) void k_head_count(Ctx C, const K *__restr
     }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_head_scan(Ctx C) {
-    __shared__ u64 s_scan[NTHREADS / 64];
+constexpr int HS_T = 1024;  // k_head_scan threads (a product's partitions in few steps)
+
+__global__ __launch_bounds__(HS_T) void k_head_scan(Ctx C) {
+    __shared__ u64 s_scan[HS_T / 64];
     for (int q = blockIdx.x; q < C.nseg; q += gridDim.x) {
         const i64 p0 = C.ppre[q], np = C.ppre[q + 1] - p0;
-        const i64 B = (np + NTHREADS - 1) / NTHREADS;  // partitions per thread, blocked
+        const i64 B = (np + HS_T - 1) / HS_T;  // partitions per thread, blocked
         const i64 b0 = p0 + (i64)threadIdx.x * B, b1 = min(p0 + np, b0 + B);
         u64 t = 0;
 #pragma unroll 8
         for (i64 p = b0; p < b1; p++) t += C.pcnt[p];
         u64 all;
-        u64 run = block_excl_scan<u64>(t, s_scan, all);
+        u64 run = block_excl_scan<u64, HS_T>(t, s_scan, all);
 #pragma unroll 8
         for (i64 p = b0; p < b1; p++) {
             const u64 v = C.pcnt[p];
@@ -965,18 +970,21 @@ __global__ __launch_bounds__(NTHREADS) void k_head_scan(Ctx C) {
 }
 
 // ---------------------------------------------------------------------------
-// k_reduce: sorted staging -> result.  A run of equal keys is summed by the
-// thread that owns its first element, left to right in staging order (for
-// FP64 that is the row-major (i, j) order of the pp-matrix, as the sort is
-// stable and SEG_RAW items start in index order), continuing past the
-// thread's items and the partition end when the run does.  Every run gets
-// the result slot given by its rank among the product's runs, which is known
-// from the keys alone: the partition's first slot comes from k_head_count and
-// k_head_scan.  A run whose
-// sum cancels to zero leaves a slot with a zero coefficient; k_zero_compact
-// removes those slots afterwards (only products that have any).  Results are
-// staged in LDS and written out contiguously with the key decompressed to the
-// packed exponent layout.
+// k_reduce: sorted staging -> result.  SEG_RAW items carry the pair index,
+// from which each term product a_i * b_j is formed.  FP64: a run of equal
+// keys is summed by the thread that owns its first element, left to right in
+// staging order (the row-major (i, j) order of the pp-matrix, as the sort is
+// stable and SEG_RAW items start in index order).  Exact rings: each thread
+// sums the runs inside its items and a segmented scan over the workgroup
+// completes the runs that cross threads.  The partition's last run is
+// followed into the next partitions by one wave, 64 items at a time, adding
+// in order.  Every run gets the result slot given by its rank among the
+// product's runs, which is known from the keys alone: the partition's first
+// slot comes from k_head_count and k_head_scan.  A run whose sum cancels to
+// zero leaves a slot with a zero coefficient; k_zero_compact removes those
+// slots afterwards (only products that have any).  Results are staged in LDS
+// and written out contiguously with the key decompressed to the packed
+// exponent layout.
 // ---------------------------------------------------------------------------
 
 // The fields of one product that the reduction uses, kept in scalar
@@ -1033,7 +1041,7 @@ __device__ inline u64 item_value_rd(const RdSeg &s, V v) {
 constexpr u32 TAG_ZCOMPACT = 201u;
 // The reduction runs 512-thread workgroups with 8 items per thread (one
 // partition of PART items): the same LDS per workgroup as 256 x 16, twice the
-// waves per CU to hide its load, gather and look-back latencies.
+// waves per CU to hide its load and gather latencies.
 constexpr int RED_T = 512, RED_IPT = PART / RED_T;
 
 template <typename K, typename V, int RING>
@@ -1589,7 +1597,7 @@ static inline int grid_for(int64_t work, int cap) { return (int)std::max<int64_t
 hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int ring, u64 *out, u32 *flags,
                         hipStream_t st) {
     ProfScope ps("stats", st);
-    hipLaunchKernelGGL(k_stats, dim3(2 * nseg), dim3(NTHREADS), 0, st, segs, nvars, bits, ring, out, flags);
+    hipLaunchKernelGGL(k_stats, dim3(2 * nseg), dim3(ST_T), 0, st, segs, nvars, bits, ring, out, flags);
     return hipGetLastError();
 }
 
@@ -1664,7 +1672,7 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
     {
         ProfScope ps("head_count", st);
         hipLaunchKernelGGL((k_head_count<K>), dim3(grid_for(P.nparts_bound, cus * 8)), dim3(NTHREADS), 0, st, C, ka);
-        hipLaunchKernelGGL(k_head_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(NTHREADS), 0, st, C);
+        hipLaunchKernelGGL(k_head_scan, dim3(grid_for(P.nseg, cus * 4)), dim3(HS_T), 0, st, C);
     }
     {
         ProfScope ps("reduce", st);
