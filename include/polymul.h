@@ -200,6 +200,16 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
 int pm_set_tuning(int32_t tile_cfg, int32_t combine, int32_t allow_dense);
 
 /*
+ * Radix digit schedule of later sorted calls (the autotuner's third knob):
+ * -1 automatic (the autotuner's choice for the size class, else 1); 0: 8-bit
+ * digits over the compressed keys' significant bits, the remainder in the
+ * last pass; 1: the same number of passes with digit widths as equal as
+ * possible (e.g. 8, 8, 7, 7 for 30 bits).  Results do not depend on it.
+ * PM_EINVAL outside -1..1.
+ */
+int pm_set_radix(int32_t digits);
+
+/*
  * Synchronises `stream`, then reports whether the last pm_mul / pm_mul_batch
  * call made by this thread hit an internal consistency check on the device
  * (a look-back wait that reached its bound, or a radix scatter position
@@ -235,17 +245,19 @@ int pm_profile_read(int32_t i, char *name, int32_t name_cap, double *total_ms, i
 
 /*
  * Autotuner.  Runs h = f * g once per candidate setting (sparse path: key
- * intervals, pair-index sort, LDS tile combine; tile shape for the degree-box
- * path), times each with
- * HIP events on `stream`, and remembers the fastest for the product's size
- * class (ring, path, floor(log2(term pairs))).  Later calls with automatic
- * settings (pm_set_tuning(-1, -1, ...), the default) use the remembered choice
- * for their largest product's class.  A setting whose workspace exceeds
- * `workspace_bytes` is skipped.  *tile_cfg and *combine (may be NULL) receive
- * the choice.  Results never depend on it.  Synchronises `stream`.
+ * intervals, pair-index sort and LDS tile combine, the two radix-sorted ones
+ * with both digit schedules of pm_set_radix; tile shape for the degree-box
+ * path), times each with HIP events on `stream`, and remembers the fastest
+ * for the product's size class (ring, path, floor(log2(term pairs))).  Later
+ * calls with automatic settings (pm_set_tuning(-1, -1, ...) and
+ * pm_set_radix(-1), the defaults) use the remembered choice for their
+ * largest product's class.  A setting whose workspace exceeds
+ * `workspace_bytes` is skipped.  *tile_cfg, *combine and *digits (each may be
+ * NULL; *digits is -1 where no radix sort runs) receive the choice.  Results
+ * never depend on it.  Synchronises `stream`.
  */
 int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
-                int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine);
+                int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine, int32_t *digits);
 /* Forget every autotuner choice. */
 void pm_autotune_reset(void);
 

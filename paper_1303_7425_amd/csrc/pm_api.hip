@@ -388,7 +388,7 @@ void pm_batch_destroy(pm_batch *b) {
 }
 
 int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
-                int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine) {
+                int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine, int32_t *digits) {
     int rc = check_args(layout, 1, f, g, h);
     if (rc) return rc;
     if (!h) return PM_EINVAL;
@@ -399,29 +399,38 @@ int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, c
     Tuning base = g_tune;
     base.tile_cfg = -1;
     base.combine = -1;
+    base.digits = -1;
     rc = mul_impl(g_stage, layout, 1, f, g, h, workspace, workspace_bytes, st, base, &P0);
     if (rc) return rc;
     if (P0.nseg < 1 || P0.segs[0].mode == SEG_EMPTY) return PM_OK;
     const bool dense = P0.segs[0].mode == SEG_DENSE;
-    std::vector<std::pair<int, int>> cands;  // (tile_cfg, combine)
+    struct Cand {
+        int tile_cfg, combine, digits;
+    };
+    std::vector<Cand> cands;  // radix-sorted settings are tried with both digit schedules
+    const int G = RADIX_DIGITS_GREEDY, B = RADIX_DIGITS_BALANCED;
     if (dense) {
-        for (int t = 0; t < N_TILE_CFGS; t++) cands.push_back({t, 0});
+        for (int t = 0; t < N_TILE_CFGS; t++) cands.push_back({t, 0, -1});
     } else if (layout->ring != PM_F64) {
-        cands.push_back({-1, 2});
-        cands.push_back({-1, 0});
-        cands.push_back({0, 1});
+        cands.push_back({-1, 2, -1});
+        cands.push_back({-1, 0, B});
+        cands.push_back({-1, 0, G});
+        cands.push_back({0, 1, B});
+        cands.push_back({0, 1, G});
     } else {
-        cands.push_back({-1, 2});
-        cands.push_back({-1, 0});
+        cands.push_back({-1, 2, -1});
+        cands.push_back({-1, 0, B});
+        cands.push_back({-1, 0, G});
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PM_EDEVICE;
     float best = 1e30f;
-    std::pair<int, int> choice = cands[0];
+    Cand choice = cands[0];
     for (auto &cd : cands) {
         Tuning t = base;
-        t.tile_cfg = cd.first;
-        t.combine = cd.second;
+        t.tile_cfg = cd.tile_cfg;
+        t.combine = cd.combine;
+        t.digits = cd.digits;
         rc = mul_impl(g_stage, layout, 1, f, g, h, workspace, workspace_bytes, st, t, nullptr);  // warm-up
         if (rc == PM_ENOMEM) {  // this setting needs more workspace than given: not a candidate
             rc = PM_OK;
@@ -448,9 +457,11 @@ int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, c
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     const uint64_t pairs = (uint64_t)f->n * (uint64_t)g->n;
-    tune_store(TuneClass{layout->ring, dense ? 1 : 0, log2_floor(pairs)}, choice.first, choice.second);
-    if (tile_cfg) *tile_cfg = choice.first;
-    if (combine) *combine = choice.second;
+    tune_store(TuneClass{layout->ring, dense ? 1 : 0, log2_floor(pairs)}, choice.tile_cfg, choice.combine,
+               choice.digits);
+    if (tile_cfg) *tile_cfg = choice.tile_cfg;
+    if (combine) *combine = choice.combine;
+    if (digits) *digits = choice.digits;
     return PM_OK;
 }
 
@@ -482,6 +493,13 @@ int pm_set_tuning(int32_t tile_cfg, int32_t combine, int32_t allow_dense) {
     g_tune.tile_cfg = tile_cfg;
     g_tune.combine = combine;
     g_tune.allow_dense = allow_dense ? 1 : 0;
+    return PM_OK;
+}
+
+int pm_set_radix(int32_t digits) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (digits < -1 || digits > 1) return PM_EINVAL;
+    g_tune.digits = digits;
     return PM_OK;
 }
 

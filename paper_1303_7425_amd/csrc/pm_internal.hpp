@@ -165,6 +165,7 @@ struct Ctx {
     i64 iv_items;
     i32 nseg, ntseg, ndseg;
     i32 nvars, bits, passes, ring;
+    unsigned char dsh[MAX_PASSES], dbits[MAX_PASSES];  // digit shift and width of each radix pass
     i64 pblk;                   // sort partitions per sort block
     i64 ntiles, ndparts;
     i32 raw;                    // sparse products carry pair indices (SEG_RAW) instead of values

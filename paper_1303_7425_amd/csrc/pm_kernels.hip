@@ -440,7 +440,8 @@ __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void
     __shared__ u32 s_h[CNT_G][RADIX];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     K *s_ck = (K *)s_dyn;
-    const int shift = pass * RADIX_BITS;
+    const int shift = C.dsh[pass];
+    const u32 dmask = (1u << C.dbits[pass]) - 1u;
     u64 *rt = C.rtot + (i64)(pass & 1) * C.nrng * RADIX;
     u64 *rz = C.rtot + (i64)((pass + 1) & 1) * C.nrng * RADIX;
     const K *ck = (const K *)C.ck;
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void
                     }
 #pragma unroll
                     for (int k = 0; k < IPT / 2; k++) {
-                        const u32 dk = (u32)(key[k] >> shift) & (RADIX - 1);
+                        const u32 dk = (u32)(key[k] >> shift) & dmask;
                         if (tid + (h + k) * NTHREADS < n) {
                             if (cnt && dk != prev) {
                                 atomicAdd(&s_h[grp][prev], cnt);
@@ -537,10 +538,10 @@ __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void
                     }
                 }
             }
-            u32 prev = (u32)(key[0] >> shift) & (RADIX - 1), cnt = 0;
+            u32 prev = (u32)(key[0] >> shift) & dmask, cnt = 0;
 #pragma unroll
             for (int k = 0; k < IPT; k++) {
-                const u32 dk = (u32)(key[k] >> shift) & (RADIX - 1);
+                const u32 dk = (u32)(key[k] >> shift) & dmask;
                 if (k < nv) {
                     if (dk != prev) {
                         atomicAdd(&s_h[grp][prev], cnt);
@@ -742,7 +743,8 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
                                              V (&val)[OS_IPT], u64 &run, const K *kf, const K *kg) {
     constexpr int NW = OsSmem<K, V, DG>::NW;
     using KS = typename OsSmem<K, V, DG>::KS;
-    const int shift = pass * RADIX_BITS;
+    const int shift = C.dsh[pass];
+    const u32 dmask = (1u << C.dbits[pass]) - 1u;
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
     const u32 w = (u32)tid >> 6;
@@ -756,7 +758,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
     // LDS operations stay in order, so the next slot reads the sum).
 #pragma unroll
     for (int k = 0; k < OS_IPT; k++) {
-        const u32 d = (u32)((key[k] >> shift) & (RADIX - 1));
+        const u32 d = (u32)((key[k] >> shift) & dmask);
         u32 t[RADIX_BITS];
         u64 m[RADIX_BITS];
 #pragma unroll
@@ -795,7 +797,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
     u32 all;
     const u32 loff = block_excl_scan<u32, OS_T>(tot, S.scan, all);
     if (dig) {
-        if (d == RADIX - 1) tot -= (u32)(PART - n);
+        if (d == dmask) tot -= (u32)(PART - n);  // the items past n rank last in the top digit
         S.loff[d] = loff;
         S.goff[d] = (u32)(run - (u64)s.lo) - loff;
         run += tot;
@@ -804,7 +806,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
     // keys and payloads into LDS in sorted order
 #pragma unroll
     for (int k = 0; k < OS_IPT; k++) {
-        const u32 dk = (u32)((key[k] >> shift) & (RADIX - 1));
+        const u32 dk = (u32)((key[k] >> shift) & dmask);
         const u32 pos = S.loff[dk] + S.wh[w][dk] + rk[k];
         S.k[pos] = DG ? (KS)dk : (KS)key[k];
         S.v[pos] = val[k];
@@ -826,7 +828,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
             const u32 i = (u32)tid + (u32)(k * OS_T);
             const KS kv = S.k[i];
             const V vv = S.v[i];
-            u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & (RADIX - 1)] + i;
+            u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & dmask] + i;
             bad |= rel >= span32;
             rel = min(rel, span32 - 1u);
             if constexpr (WK) kq[rel] = DG ? regen_key(s, kf, kg, (u32)vv) : (K)kv;
@@ -838,7 +840,7 @@ __device__ __forceinline__ void os_partition(Ctx &C, OsSmem<K, V, DG> &S, const 
             const u32 i = (u32)tid + (u32)(k * OS_T);
             if (i < (u32)n) {
                 const KS kv = S.k[i];
-                const u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & (RADIX - 1)] + i;
+                const u32 rel = S.goff[DG ? (u32)kv : (u32)(kv >> shift) & dmask] + i;
                 if (rel < span32) {
                     const V vv = S.v[i];
                     if constexpr (WK) kq[rel] = DG ? regen_key(s, kf, kg, (u32)vv) : (K)kv;
@@ -1787,6 +1789,10 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.nvars = P.nvars;
     C.bits = P.bits;
     C.passes = P.passes;
+    for (int i = 0; i < MAX_PASSES; i++) {
+        C.dsh[i] = P.dsh[i];
+        C.dbits[i] = P.dbits[i];
+    }
     C.pblk = P.pblk;
     C.ring = P.ring;
     C.ntiles = P.ntiles;

@@ -11,25 +11,50 @@
 namespace pm {
 
 static std::mutex g_tune_mu;
-static std::map<TuneClass, std::pair<int, int>> g_tune_cache;
+struct TuneChoice {
+    int tile_cfg, combine, digits;
+};
+static std::map<TuneClass, TuneChoice> g_tune_cache;
 
-bool tune_lookup(const TuneClass &c, int &tile_cfg, int &combine) {
+bool tune_lookup(const TuneClass &c, int &tile_cfg, int &combine, int &digits) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(c);
     if (it == g_tune_cache.end()) return false;
-    tile_cfg = it->second.first;
-    combine = it->second.second;
+    tile_cfg = it->second.tile_cfg;
+    combine = it->second.combine;
+    digits = it->second.digits;
     return true;
 }
 
-void tune_store(const TuneClass &c, int tile_cfg, int combine) {
+void tune_store(const TuneClass &c, int tile_cfg, int combine, int digits) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[c] = {tile_cfg, combine};
+    g_tune_cache[c] = {tile_cfg, combine, digits};
 }
 
 void tune_reset() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache.clear();
+}
+
+// Digit widths of the radix passes over the keys' significant bits: 8 bits
+// per pass with the remainder in the last (RADIX_DIGITS_GREEDY), or the same
+// number of passes with widths as equal as possible, wider ones first
+// (RADIX_DIGITS_BALANCED): fewer digit values give longer runs per digit and
+// fuller cache lines in the scatter.
+void set_digits(Plan &P, int schedule) {
+    int shift = 0;
+    for (int p = 0; p < P.passes; p++) {
+        int w;
+        if (schedule == RADIX_DIGITS_GREEDY) {
+            w = std::min(RADIX_BITS, std::max(1, P.max_bits - shift));
+        } else {
+            const int rest = std::max(P.passes, P.max_bits - shift), left = P.passes - p;
+            w = std::min(RADIX_BITS, (rest + left - 1) / left);
+        }
+        P.dsh[p] = (unsigned char)shift;
+        P.dbits[p] = (unsigned char)w;
+        shift += w;
+    }
 }
 
 int log2_floor(uint64_t x) {
@@ -142,6 +167,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     }
     P.ksize = need_u64 ? 8 : 4;
     P.passes = (max_bits + RADIX_BITS - 1) / RADIX_BITS;
+    P.max_bits = max_bits;
 
     // automatic settings: the autotuner's choice for the largest product's class
     Tuning tune = tune_in;
@@ -157,10 +183,11 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         }
         if (big >= 0) {
             TuneClass tc{ring, P.segs[big].mode == SEG_DENSE ? 1 : 0, log2_floor((uint64_t)bigp)};
-            int tcfg, comb;
-            if (tune_lookup(tc, tcfg, comb)) {
+            int tcfg, comb, dig;
+            if (tune_lookup(tc, tcfg, comb, dig)) {
                 if (tune.tile_cfg < 0) tune.tile_cfg = tcfg;
                 if (tune.combine < 0) tune.combine = comb;
+                if (tune.digits < 0) tune.digits = dig;
             }
         }
     }
@@ -197,6 +224,7 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     for (int q = 0; q < S; q++) any_sparse |= P.segs[q].mode == SEG_RAW || P.segs[q].mode == SEG_COMBINE;
     if (!any_sparse) P.passes = 0;
     if (P.raw && any_sparse && P.passes == 0) P.passes = 1;  // pass 0 also generates the items
+    set_digits(P, tune.digits == RADIX_DIGITS_GREEDY ? RADIX_DIGITS_GREEDY : RADIX_DIGITS_BALANCED);
 
     // tile shape: explicit, or the largest one that still gives >= 512 tiles
     // over the tiled products (at least two per compute unit); the sparse

@@ -28,11 +28,12 @@ struct Tuning {
     int tile_cfg = -1;       // -1: choose automatically
     int combine = -1;        // sparse path: -1 auto, 0 pair-index sort, 1 LDS tile combine + sort, 2 key intervals
     int allow_dense = 1;     // permit the degree-box path
+    int digits = -1;         // radix digit schedule: -1 auto, RADIX_DIGITS_GREEDY, RADIX_DIGITS_BALANCED
     double dense_ratio = 2;  // dense when box * dense_ratio <= na * nb
     int64_t dense_max_cells = int64_t(1) << 27;
 };
 
-// Autotuner cache: size class -> (tile_cfg, combine).  Thread-safe.
+// Autotuner cache: size class -> (tile_cfg, combine, digits).  Thread-safe.
 struct TuneClass {
     int ring, dense, log2pairs;
     bool operator<(const TuneClass &o) const {
@@ -41,10 +42,14 @@ struct TuneClass {
         return log2pairs < o.log2pairs;
     }
 };
-bool tune_lookup(const TuneClass &c, int &tile_cfg, int &combine);
-void tune_store(const TuneClass &c, int tile_cfg, int combine);
+bool tune_lookup(const TuneClass &c, int &tile_cfg, int &combine, int &digits);
+void tune_store(const TuneClass &c, int tile_cfg, int combine, int digits);
 void tune_reset();
 int log2_floor(uint64_t x);
+struct Plan;
+void set_digits(Plan &P, int schedule);
+
+enum { RADIX_DIGITS_GREEDY = 0, RADIX_DIGITS_BALANCED = 1 };
 
 struct Region {
     size_t off = 0, bytes = 0;
@@ -54,6 +59,8 @@ struct Plan {
     int nseg = 0, nvars = 0, bits = 0, ring = 0;
     int ksize = 4;
     int passes = 0;
+    int max_bits = 0;                       // significant bits of the compressed sort keys
+    unsigned char dsh[MAX_PASSES] = {}, dbits[MAX_PASSES] = {};  // digit shift and width per radix pass
     int tile_cfg = 0;
     std::vector<DevSeg> segs;
     std::vector<VarParam> vars;

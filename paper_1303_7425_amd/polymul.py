@@ -86,7 +86,8 @@ def lib():
         L.pm_batch_destroy.argtypes = [vp]
         L.pm_autotune.argtypes = [ctypes.POINTER(pm_layout), ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_cpoly),
                                   ctypes.POINTER(pm_poly), vp, i64, vp, ctypes.POINTER(ctypes.c_int32),
-                                  ctypes.POINTER(ctypes.c_int32)]
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.pm_set_radix.argtypes = [ctypes.c_int32]
         if hasattr(L, "pm_server_create"):
             L.pm_server_create.restype = vp
             L.pm_server_create.argtypes = [i64, ctypes.c_int32]
@@ -372,14 +373,19 @@ def plan_from_stats(layout, na, nb, stats):
 
 
 def autotune(layout, f: DevPoly, g: DevPoly, workspace: Workspace | None = None, stream=None):
-    """Time the candidate settings on this product; returns (tile_cfg, combine)."""
+    """Time the candidate settings on this product; returns (tile_cfg, combine, digits)."""
     call = MulCall(layout, f, g, workspace, stream)
     call.ws = (workspace or Workspace()).get(2 * call.ws_bytes)   # room for the combine setting
-    t, c = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    t, c, d = ctypes.c_int32(-1), ctypes.c_int32(-1), ctypes.c_int32(-1)
     _check(lib().pm_autotune(ctypes.byref(call.L), ctypes.byref(call.cf), ctypes.byref(call.cg),
                              ctypes.byref(call.h), ctypes.c_void_p(call.ws.data_ptr()), call.ws.numel(), call.sp,
-                             ctypes.byref(t), ctypes.byref(c)), "pm_autotune")
-    return int(t.value), int(c.value)
+                             ctypes.byref(t), ctypes.byref(c), ctypes.byref(d)), "pm_autotune")
+    return int(t.value), int(c.value), int(d.value)
+
+
+def set_radix(digits: int = -1):
+    """Radix digit schedule: -1 automatic, 0 8-bit digits, 1 balanced widths."""
+    _check(lib().pm_set_radix(int(digits)), "pm_set_radix")
 
 
 def autotune_reset():

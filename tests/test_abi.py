@@ -49,6 +49,10 @@ def test_bad_arguments_rejected_on_host(L):
     assert L.pm_set_tuning(-1, 3, 1) == pm.PM_EINVAL
     assert L.pm_set_tuning(-1, 2, 1) == pm.PM_OK
     assert L.pm_set_tuning(-1, -1, 1) == pm.PM_OK
+    assert L.pm_set_radix(2) == pm.PM_EINVAL
+    assert L.pm_set_radix(-2) == pm.PM_EINVAL
+    assert L.pm_set_radix(0) == pm.PM_OK
+    assert L.pm_set_radix(-1) == pm.PM_OK
 
 
 def stats_of(f, g):

@@ -104,6 +104,20 @@ def test_random_6var_ragged(ring, na, nb):
     check(f, g, f"rand {na}x{nb}")
 
 
+@pytest.mark.parametrize("digits", [0, 1])
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_radix_digit_schedules_same_result(ring, digits):
+    """Both digit schedules (8-bit digits, or balanced widths 8, 8, 7, 7 over
+    the 30 significant bits of this product's keys) give the oracle's result."""
+    pm = _pm()
+    f, g = W.config3(ring, n=8)
+    pm.set_radix(digits)
+    try:
+        check(f, g, f"digits={digits}")
+    finally:
+        pm.set_radix(-1)
+
+
 @pytest.mark.parametrize("ring", ["modp", "f64"])
 def test_operand_keys_beyond_radix_lds_copy(ring):
     """14,000 operand terms (56 KB of compressed keys): the digit counts copy
