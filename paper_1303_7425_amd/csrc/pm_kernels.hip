@@ -438,6 +438,7 @@ template <typename K, int SM, bool KL>
 __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void k_count(Ctx C, int pass, const K *__restrict__ kin,
                                                  const u32 *__restrict__ xin) {
     __shared__ u32 s_h[CNT_G][RADIX];
+    __shared__ u32 s_hg[RADIX];  // SM_GEN: histogram of g's low digit, per product
     extern __shared__ __align__(16) unsigned char s_dyn[];
     K *s_ck = (K *)s_dyn;
     const int shift = C.dsh[pass];
@@ -461,6 +462,13 @@ __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void
                 __syncthreads();  // the previous product's copy is no longer read
                 for (i64 t = threadIdx.x; t < m; t += CNT_T) s_ck[t] = ck[sq.ck_f + t];
             }
+            if constexpr (SM == SM_GEN) {
+                __syncthreads();
+                if (grp == 0) s_hg[tid] = 0;
+                __syncthreads();
+                const K *g0 = KL ? s_ck + (sq.ck_g - sq.ck_f) : ck + sq.ck_g;
+                for (i64 t = threadIdx.x; t < sq.nb; t += CNT_T) atomicAdd(&s_hg[(u32)g0[t] & dmask], 1u);
+            }
         }
         const i64 bl = b - C.chpre[q];
         const i64 r = C.rpre[q] + bl / RNG;
@@ -470,7 +478,35 @@ __global__ __launch_bounds__(CNT_T) __attribute__((amdgpu_waves_per_eu(6))) void
         const K *kg = kf + (sq.ck_g - sq.ck_f);
         if (grp == 0 && bl % RNG == 0) rz[r * RADIX + tid] = 0;
         __syncthreads();
-        for (i64 p = p0 + grp; p < p1; p += CNT_G) {
+        if constexpr (SM == SM_GEN) {
+            // Pass 0 counts the block's pairs x in [x0, x1) in generation
+            // order (shift 0).  The digit of a_i + b_j is that of (a_i mod
+            // 2^w) + (b_j mod 2^w), so a full row i of g contributes g's
+            // low-digit histogram rotated by a_i: count[t] += hg[(t - a_i) mod 2^w].
+            // Partial rows at the block's ends (and products with short
+            // rows) are counted item by item.
+            const u32 nb = sq.nb;
+            const u32 x0 = (u32)((p0 - sq.first) * PART);
+            const u32 x1 = (u32)min(sq.n_q, (p1 - sq.first) * PART);
+            const u32 i0 = div32(x0, sq.nb_div), i1 = div32(x1 - 1, sq.nb_div);
+            const bool rows = nb >= 4 * RADIX && i1 >= i0 + 2;
+            const u32 e0 = rows ? (i0 + 1) * nb : x1;  // end of the first directly counted range
+            const u32 s1 = rows ? i1 * nb : x1;        // start of the second
+            for (u32 x = x0 + threadIdx.x; x < e0; x += CNT_T) {
+                const u32 i = div32(x, sq.nb_div);
+                atomicAdd(&s_h[0][(u32)(kf[i] + kg[x - i * nb]) & dmask], 1u);
+            }
+            for (u32 x = s1 + threadIdx.x; x < x1; x += CNT_T) {
+                const u32 i = div32(x, sq.nb_div);
+                atomicAdd(&s_h[0][(u32)(kf[i] + kg[x - i * nb]) & dmask], 1u);
+            }
+            if (rows && grp == 0 && (u32)tid <= dmask) {
+                u32 acc = 0;
+                for (u32 i = i0 + 1; i < i1; i++) acc += s_hg[((u32)tid - (u32)kf[i]) & dmask];
+                if (acc) atomicAdd(&s_h[0][tid], acc);
+            }
+        }
+        for (i64 p = p0 + grp; SM != SM_GEN && p < p1; p += CNT_G) {
             const i64 c = p - sq.first;
             const int n = (int)min((i64)PART, sq.n_q - c * PART);
             if constexpr (SM == SM_GEN) {

@@ -118,6 +118,28 @@ def test_radix_digit_schedules_same_result(ring, digits):
         pm.set_radix(-1)
 
 
+@pytest.mark.parametrize("digits", [0, 1])
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_generated_pass_counts_with_narrow_digits(ring, digits):
+    """Long rows of g (1089 terms) in a small degree box (11 key bits, two
+    radix passes of 6 and 5 bits when balanced): the first pass counts whole
+    rows from g's rotated digit histogram and partial rows item by item."""
+    pm = _pm()
+    rng = W.rng_for(57)
+    lay = W.Layout(2, 8, ring)
+    ge = np.array([(a, b) for a in range(33) for b in range(33)], dtype=np.int64)
+    fe = np.unique(rng.integers(0, 12, size=(40, 2)), axis=0)[:20]
+    coef = {"modp": lambda n: W.residues(rng, n), "f64": lambda n: W.uniform_pm1(rng, n)}[ring]
+    g = W.Poly(lay, W.pack(ge, 2, 8), coef(len(ge)))
+    f = W.Poly(lay, W.pack(fe, 2, 8), coef(len(fe)))
+    pm.set_tuning(-1, -1, False)  # keep it off the degree-box path
+    pm.set_radix(digits)
+    try:
+        check(f, g, f"narrow digits={digits}")
+    finally:
+        pm.set_radix(-1)
+
+
 @pytest.mark.parametrize("ring", ["modp", "f64"])
 def test_operand_keys_beyond_radix_lds_copy(ring):
     """14,000 operand terms (56 KB of compressed keys): the digit counts copy
