@@ -60,6 +60,21 @@ def test_batch_with_large_operand_keys(ring):
     check_results(pairs, res, ring)
 
 
+@pytest.mark.parametrize("ring", ["modp", "f64"])
+def test_batch_many_small_operand_keys(ring):
+    """Forty products whose compressed operand keys each fit the LDS copies
+    but total over 1 MB: the passes carry keys with the pair indices."""
+    pm = _pm()
+    rng = W.rng_for(78)
+    pairs = [(W.random_sparse(rng, 8000, 6, 10, 15, ring), W.random_sparse(rng, 4, 6, 10, 15, ring))
+             for _ in range(40)]
+    print(f"[batch] many products, keys in LDS, ring={ring}", flush=True)
+    res = pm.mul_batch((6, 10, ring), [pm.to_device(f) for f, _ in pairs], [pm.to_device(g) for _, g in pairs])
+    assert pm.last_call_status() == 0
+    assert pm.last_call_info()["payload_bytes"] == 4
+    check_results(pairs, res, ring)
+
+
 def test_batch_with_dense_and_sparse_members():
     pm = _pm()
     # (1+x+y+z+t+u)^10 times itself plus one takes the degree-box path; the
