@@ -255,25 +255,31 @@ def bench_serve(args):
             tickets.append(owner[slot])
         for t in tickets:
             assert srv.wait(t) == 0
-        return time.perf_counter() - t0
+        return time.perf_counter() - t0, tickets
 
     # saturation: all requests at once
     lat0 = len(srv.latencies_us())
-    t_sat = run(1e12)
+    t_sat, _ = run(1e12)
     pairs = sum(len(r.f) * len(r.g) for r in reqs_all)
     sat_rate = n_req / t_sat
     log(f"[serve] saturated: {sat_rate:.1f} req/s, {pairs / t_sat:.3e} pairs/s")
     lat1 = len(srv.latencies_us())
     rate = args.serve_load * sat_rate
-    t_run = run(rate)
+    t_run, tickets = run(rate)
     lat = np.array(srv.latencies_us()[lat1:])
+    # the same latencies by request class (ticket i is request i)
+    per_class = {}
+    for kind in sorted({r.kind for r in reqs_all}):
+        lk = np.array([srv.latency_us(t) for t, r in zip(tickets, reqs_all) if r.kind == kind])
+        per_class[kind] = {"requests": int(lk.size), "p50_ms": float(np.percentile(lk, 50)) / 1e3,
+                           "p99_ms": float(np.percentile(lk, 99)) / 1e3}
     srv.close()
     return {
         "metric": "serve latency p50/p99", "value": float(np.percentile(lat, 50)) / 1e3, "unit": "ms (p50)",
         "p99_ms": float(np.percentile(lat, 99)) / 1e3, "n_gpus": 1, "higher_is_better": False, "dtype": "u64",
         "data": "synthetic", "arrival_rate_per_s": rate, "load_fraction_of_saturation": args.serve_load,
         "saturated_requests_per_s": sat_rate, "saturated_term_products_per_s": pairs / t_sat,
-        "sustained_term_products_per_s": pairs / t_run, "requests": n_req,
+        "sustained_term_products_per_s": pairs / t_run, "requests": n_req, "latency_by_class": per_class,
         "config": {"workload": "Poisson arrivals (seed 5): 98% sparse 5-var pairs at power U{6..12} with fresh "
                                "residues, 2% dense (1+x+y+z+t)^30 x (same+1), mod 2^61-1"},
     }

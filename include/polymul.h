@@ -161,7 +161,11 @@ void pm_batch_destroy(pm_batch *b);
  *            *status receives the request's own return code.
  *   wait:    blocks until the ticket completes.
  *   stats:   latency (submit -> completion observed by the scheduler) of all
- *            completed requests, in microseconds, up to `cap` entries.
+ *            completed requests, in microseconds, up to `cap` entries, in
+ *            completion order; returns the number recorded.
+ *   latency: the same latency for one ticket, once it has completed (with
+ *            any status): PM_EBUSY while it is still running, PM_EINVAL for
+ *            an unknown ticket or a NULL pointer.
  *   destroy: waits for all outstanding work and frees the arena.
  */
 typedef struct pm_server pm_server;
@@ -171,6 +175,7 @@ int pm_server_submit(pm_server *s, const pm_layout *layout, const pm_cpoly *f, c
 int pm_server_poll(pm_server *s, uint64_t ticket, int32_t *done, int32_t *status);
 int pm_server_wait(pm_server *s, uint64_t ticket, int32_t *status);
 int64_t pm_server_latencies(pm_server *s, double *latency_us, int64_t cap);
+int pm_server_latency(pm_server *s, uint64_t ticket, double *latency_us);
 void pm_server_destroy(pm_server *s);
 
 /*

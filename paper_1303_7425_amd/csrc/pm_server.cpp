@@ -82,6 +82,7 @@ struct Request {
     pm_cpoly f, g;
     pm_poly h;
     double t_submit;
+    double latency = 0;  // completion seen by the scheduler minus submission, microseconds
     int status = PM_OK;
     bool done = false;
 };
@@ -120,8 +121,9 @@ struct pm_server {
 
 static void finish(pm_server *s, Request *r, int status, double t) {
     r->status = status;
+    r->latency = t - r->t_submit;
     r->done = true;
-    if (status == PM_OK) s->latencies.push_back(t - r->t_submit);
+    if (status == PM_OK) s->latencies.push_back(r->latency);
 }
 
 static void scheduler(pm_server *s) {
@@ -351,6 +353,16 @@ int pm_server_wait(pm_server *s, uint64_t ticket, int32_t *status) {
     Request *r = it->second;
     s->cv_done.wait(lk, [&] { return r->done; });
     if (status) *status = r->status;
+    return PM_OK;
+}
+
+int pm_server_latency(pm_server *s, uint64_t ticket, double *latency_us) {
+    if (!s || !latency_us) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return PM_EINVAL;
+    if (!it->second->done) return PM_EBUSY;
+    *latency_us = it->second->latency;
     return PM_OK;
 }
 

@@ -99,6 +99,7 @@ def lib():
             L.pm_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
             L.pm_server_latencies.restype = i64
             L.pm_server_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64]
+            L.pm_server_latency.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
             L.pm_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
@@ -421,6 +422,12 @@ class Server:
         s = ctypes.c_int32(0)
         _check(lib().pm_server_wait(self.h, ticket, ctypes.byref(s)), "pm_server_wait")
         return int(s.value)
+
+    def latency_us(self, ticket: int) -> float:
+        """Submit-to-completion latency of one completed ticket (microseconds)."""
+        v = ctypes.c_double(0)
+        _check(lib().pm_server_latency(self.h, ticket, ctypes.byref(v)), "pm_server_latency")
+        return float(v.value)
 
     def latencies_us(self):
         n = lib().pm_server_latencies(self.h, None, 0)

@@ -53,6 +53,8 @@ def test_bad_arguments_rejected_on_host(L):
     assert L.pm_set_radix(-2) == pm.PM_EINVAL
     assert L.pm_set_radix(0) == pm.PM_OK
     assert L.pm_set_radix(-1) == pm.PM_OK
+    lat = ctypes.c_double(0)
+    assert L.pm_server_latency(None, 1, ctypes.byref(lat)) == pm.PM_EINVAL
 
 
 def stats_of(f, g):

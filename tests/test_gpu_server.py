@@ -38,6 +38,11 @@ def test_server_mix_matches_alone_and_oracle():
     torch.cuda.synchronize()
     lat = srv.latencies_us()
     assert len(lat) == len(reqs)
+    # per-ticket latencies: the same values as the completion-order record
+    per = [srv.latency_us(t) for t in tickets]
+    assert sorted(per) == sorted(lat) and min(per) > 0
+    with pytest.raises(pm.PolymulError):
+        srv.latency_us(max(tickets) + 1000)
     for i, r in enumerate(reqs):
         k, c, n = outs[i]
         nn = int(n.item())
