@@ -61,7 +61,7 @@ extern "C" {
 #define PM_EOVERFLOW (-3)  /* max_f[v] + max_g[v] does not fit the field of variable v */
 #define PM_ERANGE (-4)     /* residue >= p (PM_MODP61) or non-finite coefficient (PM_F64) */
 #define PM_ECAPACITY (-5)  /* output capacity below the bound (pm_server_submit only) */
-#define PM_ENOMEM (-6)     /* workspace too small, or server arena cannot ever hold the request */
+#define PM_ENOMEM (-6)     /* workspace too small, a sparse product of more than 2^32 - 1 term pairs, or a server arena that can never hold the request */
 #define PM_EDEVICE (-7)    /* HIP runtime error; pm_last_error() has the message */
 #define PM_EBUSY (-8)      /* server: request queue full, retry later */
 

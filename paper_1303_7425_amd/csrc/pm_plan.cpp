@@ -220,6 +220,11 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.vsize = combine ? 8 : 4;
     for (int q = 0; q < S; q++)
         if (P.segs[q].mode == SEG_RAW && combine) P.segs[q].mode = SEG_COMBINE;
+    // the combine path stages at most one item per term pair and addresses a
+    // product's staging slots and sort partitions with 32-bit positions
+    for (int q = 0; q < S; q++)
+        if (P.segs[q].mode == SEG_COMBINE && (unsigned __int128)P.segs[q].na * P.segs[q].nb > 0xFFFFFFFFull)
+            return PM_ENOMEM;
     bool any_sparse = false;
     for (int q = 0; q < S; q++) any_sparse |= P.segs[q].mode == SEG_RAW || P.segs[q].mode == SEG_COMBINE;
     if (!any_sparse) P.passes = 0;

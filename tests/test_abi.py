@@ -107,4 +107,16 @@ def test_plan_fp64_too_many_pairs():
     rc, _, _ = pm.plan_from_stats((1, 32, "f64"), [1 << 17], [1 << 16], st[None, :])
     assert rc == pm.PM_ENOMEM                          # more than 2^32 - 1 FP64 term pairs in one product
     rc, _, _ = pm.plan_from_stats((1, 32, "modp"), [1 << 17], [1 << 16], st[None, :])
-    assert rc == pm.PM_OK                              # exact rings fall back to the LDS combine
+    assert rc == pm.PM_OK                              # a degree box this small takes the dense path
+
+
+def test_plan_sparse_exact_too_many_pairs():
+    # 2 variables x 32 bits, exponents up to 2^20: the degree box (about 2^42
+    # cells) is far larger than the 2^33 term pairs, so the product is sparse;
+    # its staged positions would not fit 32 bits, which the planner refuses
+    st = np.array([0, 0, 1 << 20, 1 << 20, 0, 0, 1 << 20, 1 << 20], dtype=np.uint64)
+    for ring in ("modp", "i64", "f64"):
+        rc, _, _ = pm.plan_from_stats((2, 32, ring), [1 << 17], [1 << 16], st[None, :])
+        assert rc == pm.PM_ENOMEM, ring
+    rc, _, _ = pm.plan_from_stats((2, 32, "modp"), [1 << 16], [(1 << 16) - 1], st[None, :])
+    assert rc == pm.PM_OK                              # 2^31 pairs still fit
