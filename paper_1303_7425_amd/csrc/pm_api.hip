@@ -181,6 +181,9 @@ int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st) {
     memcpy(pin + (P.o_cpre - d0), P.cpre.data(), 8 * P.cpre.size());
     memcpy(pin + (P.o_iv_pre - d0), P.iv_pre.data(), 8 * P.iv_pre.size());
     if (!P.iv_seg.empty()) memcpy(pin + (P.o_iv_seg - d0), P.iv_seg.data(), 4 * P.iv_seg.size());
+    if (!P.bk_tile_pre.empty()) memcpy(pin + (P.o_bk_tile_pre - d0), P.bk_tile_pre.data(), 8 * P.bk_tile_pre.size());
+    if (!P.bk_seg.empty()) memcpy(pin + (P.o_bk_seg - d0), P.bk_seg.data(), 4 * P.bk_seg.size());
+    if (!P.bk_sb_pre.empty()) memcpy(pin + (P.o_bk_sb_pre - d0), P.bk_sb_pre.data(), 8 * P.bk_sb_pre.size());
     hipError_t e = hipMemcpyAsync((char *)ws + d0, pin, P.r_desc.bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(hs.ev, st);
     if (e != hipSuccess) {
@@ -489,7 +492,7 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
 
 int pm_set_tuning(int32_t tile_cfg, int32_t combine, int32_t allow_dense) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (tile_cfg < -1 || tile_cfg >= N_TILE_CFGS || combine < -1 || combine > 2) return PM_EINVAL;
+    if (tile_cfg < -1 || tile_cfg >= N_TILE_CFGS || combine < -1 || combine > 3) return PM_EINVAL;
     g_tune.tile_cfg = tile_cfg;
     g_tune.combine = combine;
     g_tune.allow_dense = allow_dense ? 1 : 0;

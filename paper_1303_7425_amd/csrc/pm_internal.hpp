@@ -23,6 +23,30 @@ enum SegMode : int {
     SEG_RAW = 2,      // pair indices sorted by key (products regenerated), then reduction
     SEG_DENSE = 3,    // accumulated directly into the degree box, then compaction
     SEG_IVAL = 4,     // output-key intervals owned by workgroups, merged in LDS (no global sort)
+    SEG_BKT = 5,      // pairs scattered once into output-key work items, each sorted and summed in LDS
+};
+
+// Output-key work items (SEG_BKT).  The compressed key range of a product is
+// cut into fine bins of 2^fs keys; a counting pass over the term pairs gives
+// each bin's pair count, consecutive bins are grouped greedily into work
+// items of at most BK_CAP pairs (a single bin over BK_CAP forms its own), one
+// pass scatters every pair into its work item, and one workgroup per work
+// item sorts and sums it in LDS.
+constexpr int BK_TILE = 8192;          // term pairs per generation tile (rows x power-of-two columns)
+constexpr int BK_TN_MAX = 256;         // columns of a generation tile, at most
+constexpr int BK_SB_LOG = 12;
+constexpr int BK_SB = 1 << BK_SB_LOG;  // fine bins per super-bin (the unit of the greedy cut)
+constexpr int BK_CAP = 8192;           // pairs of a work item sorted in one LDS pass
+constexpr int BK_BIN_PAIRS = 8;        // about this many term pairs per fine bin
+
+// One work item: fine bins [bin_lo, bin_hi) of product q (bins local to the
+// product), its items at [off, end) of the staging array.
+struct BkWi {
+    u32 bin_lo, bin_hi;
+    u64 off, end;
+    i32 q;
+    u32 first, last;  // the product's first / last work item
+    u32 pad;
 };
 
 constexpr int IV_SAMPLES_MAX = 4096;   // grid samples per product ((l+1)^2, l <= 63)
@@ -95,6 +119,12 @@ struct DevSeg {
     i64 var_off;                   // offset of this product's VarParam entries
     i64 iv_l;                      // grid parameter l (SEG_IVAL): (l+1)^2 samples
     i64 iv_samp_off, iv_spl_off;   // offsets of its samples and splitters
+    i64 bk_bin_off;                // SEG_BKT: first fine bin in the launch's bin arrays (multiple of BK_SB)
+    i64 bk_sb_first, bk_nsb;       // first super-bin (launch-wide index) and super-bins
+    i64 bk_tile_first;             // first generation tile
+    i64 bk_tiles_n;                // generation tiles along g
+    i32 bk_fs;                     // fine shift: bin = compressed key >> bk_fs
+    i32 bk_tnl;                    // log2 of the generation tile's columns (rows: BK_TILE >> bk_tnl)
     u64 lo_key;                    // packed key of the smallest output exponent vector
     u64 *hk, *hc;                  // result arrays
     i64 *n_out;
@@ -169,6 +199,31 @@ struct Ctx {
     i64 pblk;                   // sort partitions per sort block
     i64 ntiles, ndparts;
     i32 raw;                    // sparse products carry pair indices (SEG_RAW) instead of values
+    // SEG_BKT (output-key work items)
+    u32 *bk_hist;               // [bins] term pairs per fine bin (zeroed per call)
+    unsigned short *bk_wbin;    // [bins] work item of each bin, numbered inside its super-bin
+    u32 *bk_sbtot, *bk_sbwi;    // [nsb] pairs and work items of each super-bin
+    u32 *bk_sbtb;               // [nsb+1] first work item (ticket) of each super-bin; [nsb]: all
+    u64 *bk_sbpre;              // [nsb] first staging slot of each super-bin
+    BkWi *bk_wi;                // [wi bound] work items by ticket
+    u32 *bk_fill;               // [wi bound] staged items per work item so far (zeroed per call)
+    u64 *bk_fatc;               // result coefficients of work items over BK_CAP pairs
+    u64 *bk_fbase;              // [wi bound] their first slot in bk_fatc
+    u64 *bk_fatfill;            // slots of bk_fatc taken (zeroed per call)
+    i64 bk_fat_cap;             // slots of bk_fatc
+    u64 *bk_stage;              // staged items: (pair index << 32) | compressed key; then result coefficients
+    u32 *bk_rkey;               // [staging slots] compressed keys of the result terms
+    u32 *bk_u;                  // [wi bound] result terms of each work item (bit 31: coefficients in bk_fatc)
+    u64 *bk_opre;               // [wi bound] first result slot of each work item
+    u64 *bk_tlist;              // [tiles][BK_TL] (bin << 32 | pairs) of each generation tile
+    u32 *bk_tcnt;               // [tiles] entries of the tile's list (all ones: not listed)
+    const i64 *bk_tile_pre;     // [nbk+1] generation-tile prefix over SEG_BKT products
+    const i32 *bk_seg;          // [nbk] their segment indices
+    const i64 *bk_sb_pre;       // [nbk+1] super-bin prefix over SEG_BKT products
+    i32 nbk;
+    i64 bk_ntiles, bk_nsb;
+    i64 bk_wi_bound;            // work-item slots (tickets beyond are an internal error)
+    i64 bk_nstage;              // staging slots
     i32 tb_tile, tb_sort, tb_cmp;  // consecutive work items handed out per work-queue ticket
 };
 
@@ -183,6 +238,7 @@ enum Counter : int {
     CNT_ERR_SPIN,                   // a lookback wait hit its iteration bound
     CNT_ZEROS,                      // some product of the launch has cancelled terms
     CNT_ZCOMPACT,
+    CNT_BK_REDUCE,                  // work items of the in-LDS sort and sum
     CNT_COUNT
 };
 

@@ -1506,6 +1506,8 @@ __global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
 }  // namespace pm
 
 #include "pm_ival.hpp"
+#include "pm_bkt.hpp"
+static_assert(pm::BK_TL == 512, "workspace layout sizes the tile lists for 512 bins");
 
 // ===========================================================================
 // Host-side launch sequence
@@ -1721,6 +1723,33 @@ static void launch_sort_reduce(const Plan &P, const Ctx &C, hipStream_t st, int 
     hipLaunchKernelGGL((k_zero_compact<RING>), dim3(grid_for(P.nparts_bound, cus * 2)), dim3(NTHREADS), 0, st, C);
 }
 
+template <int RING>
+static void launch_bkt(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
+    {
+        ProfScope ps("bk_count", st);
+        hipLaunchKernelGGL(k_bk_count, dim3(grid_for(P.bk_ntiles, cus * 8)), dim3(BK_T), 0, st, C);
+    }
+    {
+        ProfScope ps("bk_cut", st);
+        hipLaunchKernelGGL(k_bk_cut, dim3(P.bk_nsb), dim3(BC_T), 0, st, C);
+        hipLaunchKernelGGL(k_bk_scan, dim3(1), dim3(BC_T), 0, st, C);
+        hipLaunchKernelGGL(k_bk_winfo, dim3(P.bk_nsb), dim3(BC_T), 0, st, C);
+    }
+    {
+        ProfScope ps("bk_scatter", st);
+        hipLaunchKernelGGL(k_bk_scatter, dim3(grid_for(P.bk_ntiles, cus * 8)), dim3(BK_T), 0, st, C);
+    }
+    {
+        ProfScope ps("bk_reduce", st);
+        // resident workgroups per CU: LDS allows two for the exact rings (about 72 KB each), one for FP64
+        const int per_cu = RING == RING_F64 ? 1 : std::max(1, 1024 / BR_T);
+        hipLaunchKernelGGL((k_bk_reduce<RING>), dim3(grid_for(P.bk_wi_bound, cus * per_cu)), dim3(BR_T), 0, st, C);
+    }
+    ProfScope ps("bk_place", st);
+    hipLaunchKernelGGL(k_bk_oscan, dim3(1), dim3(BC_T), 0, st, C);
+    hipLaunchKernelGGL(k_bk_copy, dim3(grid_for(P.bk_wi_bound, cus * 8)), dim3(BK_T), 0, st, C);
+}
+
 template <typename K, int RING>
 static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
     if (P.nck > 0) {
@@ -1746,6 +1775,9 @@ static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
             hipLaunchKernelGGL(k_ival_scan, dim3(P.nival), dim3(NTHREADS), 0, st, C);
             hipLaunchKernelGGL((k_ival_copy<K>), dim3(grid_for(P.iv_items, cus * 8)), dim3(NTHREADS), 0, st, C);
         }
+    }
+    if (P.nbk > 0) {
+        if constexpr (sizeof(K) == 4) launch_bkt<RING>(P, C, st, cus);
     }
     if (P.nsparse > 0) {
         if (P.raw) {
@@ -1851,6 +1883,32 @@ Ctx make_ctx(const Plan &P, void *ws) {
     C.tb_sort = 1;
     C.tb_cmp = 1;
     C.ndparts = P.ndparts;
+    C.bk_hist = (u32 *)(b + P.o_bk_hist);
+    C.bk_wbin = (unsigned short *)(b + P.o_bk_wbin);
+    C.bk_sbtot = (u32 *)(b + P.o_bk_sbtot);
+    C.bk_sbwi = (u32 *)(b + P.o_bk_sbwi);
+    C.bk_sbtb = (u32 *)(b + P.o_bk_sbtb);
+    C.bk_sbpre = (u64 *)(b + P.o_bk_sbpre);
+    C.bk_wi = (BkWi *)(b + P.o_bk_wi);
+    C.bk_fill = (u32 *)(b + P.o_bk_fill);
+    C.bk_fatc = (u64 *)(b + P.o_bk_fatc);
+    C.bk_fbase = (u64 *)(b + P.o_bk_fbase);
+    C.bk_fatfill = (u64 *)(b + P.o_bk_fatfill);
+    C.bk_fat_cap = P.bk_fat_cap;
+    C.bk_stage = (u64 *)(b + P.o_bk_stage);
+    C.bk_rkey = (u32 *)(b + P.o_bk_rkey);
+    C.bk_u = (u32 *)(b + P.o_bk_u);
+    C.bk_opre = (u64 *)(b + P.o_bk_opre);
+    C.bk_tlist = (u64 *)(b + P.o_bk_tlist);
+    C.bk_tcnt = (u32 *)(b + P.o_bk_tcnt);
+    C.bk_tile_pre = (const i64 *)(b + P.o_bk_tile_pre);
+    C.bk_seg = (const i32 *)(b + P.o_bk_seg);
+    C.bk_sb_pre = (const i64 *)(b + P.o_bk_sb_pre);
+    C.nbk = P.nbk;
+    C.bk_ntiles = P.bk_ntiles;
+    C.bk_nsb = P.bk_nsb;
+    C.bk_wi_bound = P.bk_wi_bound;
+    C.bk_nstage = P.bk_nstage;
     return C;
 }
 

@@ -214,6 +214,24 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             d.iv_l = l;
         }
     }
+    // output-key work items: products with 32-bit compressed keys and pair
+    // indices whose single monomials can never hold more than BK_CAP pairs
+    // (at most min(na, nb) pairs share a monomial)
+    if (P.ksize == 4 && (tune.combine == -1 || tune.combine == 3)) {
+        for (int q = 0; q < S; q++) {
+            DevSeg &d = P.segs[q];
+            if (d.mode != SEG_RAW) continue;
+            if ((unsigned __int128)d.na * d.nb > 0xFFFFFFFFull || std::min(d.na, d.nb) > BK_CAP) continue;
+            d.mode = SEG_BKT;
+        }
+        idx_fits = true;
+        sentinel_ok = true;
+        for (int q = 0; q < S; q++) {
+            if (P.segs[q].mode != SEG_RAW) continue;
+            if ((unsigned __int128)P.segs[q].na * P.segs[q].nb > 0xFFFFFFFFull) idx_fits = false;
+            if (box[q] >= ((unsigned __int128)1 << 64)) sentinel_ok = false;
+        }
+    }
     bool combine = ring != RING_F64 && sentinel_ok && (tune.combine == 1 || !idx_fits);
     if (!combine && !idx_fits) return PM_ENOMEM;  // FP64 product of more than 2^32 - 1 term pairs
     P.raw = combine ? 0 : 1;
@@ -299,6 +317,43 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             P.nparts_bound += (d.stage_bound + PART - 1) / PART;
             P.nsparse++;
         }
+        if (d.mode == SEG_BKT) {
+            // fine bins of about BK_BIN_PAIRS pairs each (at least one super-bin)
+            const uint64_t pairs = (uint64_t)d.na * (uint64_t)d.nb;
+            const uint64_t target = std::max<uint64_t>(BK_SB, pairs / BK_BIN_PAIRS);
+            const uint64_t cells = (uint64_t)box[q];
+            int fs = 0;
+            while (((cells + (1ull << fs) - 1) >> fs) > target) fs++;
+            const int64_t nbins = (int64_t)((cells + (1ull << fs) - 1) >> fs);
+            const int64_t nsb = (nbins + BK_SB - 1) / BK_SB;
+            d.bk_fs = fs;
+            d.bk_bin_off = P.bk_nbins;
+            d.bk_sb_first = P.bk_nsb;
+            d.bk_nsb = nsb;
+            P.bk_nbins += nsb * BK_SB;
+            P.bk_nsb += nsb;
+            // generation tiles: up to BK_TN_MAX columns (a power of two), BK_TILE slots
+            int tnl = 0;
+            while ((1ll << tnl) < d.nb && (1 << tnl) < BK_TN_MAX) tnl++;
+            d.bk_tnl = tnl;
+            const int64_t tm = BK_TILE >> tnl, tn = 1ll << tnl;
+            d.bk_tiles_n = (d.nb + tn - 1) / tn;
+            d.bk_tile_first = P.bk_ntiles;
+            if (P.bk_tile_pre.empty()) P.bk_tile_pre.push_back(0), P.bk_sb_pre.push_back(0);
+            P.bk_ntiles += ((d.na + tm - 1) / tm) * d.bk_tiles_n;
+            P.bk_tile_pre.push_back(P.bk_ntiles);
+            P.bk_sb_pre.push_back(P.bk_nsb);
+            P.bk_seg.push_back(q);
+            // two consecutive work items of a super-bin hold more than BK_CAP
+            // pairs, so a super-bin of p pairs has at most 2 ceil(p / BK_CAP) + 1
+            P.bk_wi_bound += 2 * (int64_t)((pairs + BK_CAP - 1) / BK_CAP) + 3 * nsb + 1;
+            P.bk_nstage += (int64_t)pairs;
+            // a work item over BK_CAP pairs is one fine bin: at most 2^fs result terms
+            const uint64_t fat_items = pairs / (BK_CAP + 1);
+            P.bk_fat_cap += (int64_t)std::min<uint64_t>(pairs, fat_items << fs);
+            d.nb_div = make_div32((uint32_t)d.nb);
+            P.nbk++;
+        }
         if (d.mode == SEG_DENSE) {
             d.stage_base = nbox;
             d.stage_bound = (int64_t)box[q];
@@ -358,6 +413,9 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_cpre = take(8 * P.cpre.size());
     P.o_iv_pre = take(8 * P.iv_pre.size());
     P.o_iv_seg = take(4 * std::max<size_t>(1, P.iv_seg.size()));
+    P.o_bk_tile_pre = take(8 * std::max<size_t>(1, P.bk_tile_pre.size()));
+    P.o_bk_seg = take(4 * std::max<size_t>(1, P.bk_seg.size()));
+    P.o_bk_sb_pre = take(8 * std::max<size_t>(1, P.bk_sb_pre.size()));
     P.r_desc.off = desc0;
     P.r_desc.bytes = off - desc0;
     const size_t zero0 = off;
@@ -367,6 +425,9 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_look_cmp = take((size_t)8 * std::max<int64_t>(1, P.ndparts));
     P.o_look_tile = take((size_t)8 * std::max<int64_t>(1, P.ntiles));
     P.o_box = take((size_t)8 * std::max<int64_t>(1, nbox));
+    P.o_bk_hist = take((size_t)4 * std::max<int64_t>(1, P.bk_nbins));
+    P.o_bk_fill = take((size_t)4 * std::max<int64_t>(1, P.bk_wi_bound));
+    P.o_bk_fatfill = take(8);
     // sort blocks fill the radix passes' resident workgroups
     P.kl = P.raw && P.ix && os_keys_in_lds(P.ck_lds, P.ksize, P.vsize);
     const int64_t resident = (int64_t)cus * (P.kl ? 2 : os_resident(P.ksize, P.vsize));
@@ -410,6 +471,20 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     P.o_iv_items = take((size_t)16 * std::max<int64_t>(1, P.iv_items));
     P.o_iv_off = take((size_t)8 * std::max<int64_t>(1, P.iv_items));
     P.o_ck = take((size_t)P.ksize * std::max<int64_t>(1, nck));
+    P.o_bk_wbin = take((size_t)2 * std::max<int64_t>(1, P.bk_nbins));
+    P.o_bk_sbtot = take((size_t)4 * std::max<int64_t>(1, P.bk_nsb));
+    P.o_bk_sbwi = take((size_t)4 * std::max<int64_t>(1, P.bk_nsb));
+    P.o_bk_sbtb = take((size_t)4 * (P.bk_nsb + 1));
+    P.o_bk_sbpre = take((size_t)8 * std::max<int64_t>(1, P.bk_nsb));
+    P.o_bk_wi = take(sizeof(BkWi) * std::max<int64_t>(1, P.bk_wi_bound));
+    P.o_bk_stage = take((size_t)8 * std::max<int64_t>(1, P.bk_nstage));
+    P.o_bk_rkey = take((size_t)4 * std::max<int64_t>(1, P.bk_nstage));
+    P.o_bk_tlist = take((size_t)8 * 512 * std::max<int64_t>(1, P.bk_ntiles));  // BK_TL bins per tile
+    P.o_bk_tcnt = take((size_t)4 * std::max<int64_t>(1, P.bk_ntiles));
+    P.o_bk_u = take((size_t)4 * std::max<int64_t>(1, P.bk_wi_bound));
+    P.o_bk_opre = take((size_t)8 * std::max<int64_t>(1, P.bk_wi_bound));
+    P.o_bk_fbase = take((size_t)8 * std::max<int64_t>(1, P.bk_wi_bound));
+    P.o_bk_fatc = take((size_t)8 * std::max<int64_t>(1, P.bk_fat_cap));
     const int64_t nstageA = P.nival ? 1 : nstage;
     P.o_stAk = take((size_t)P.ksize * std::max<int64_t>(1, nstageA));
     P.o_stAv = take((size_t)P.vsize * std::max<int64_t>(1, nstageA));

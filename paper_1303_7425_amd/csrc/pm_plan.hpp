@@ -26,7 +26,8 @@ constexpr int N_TILE_CFGS = 3;
 
 struct Tuning {
     int tile_cfg = -1;       // -1: choose automatically
-    int combine = -1;        // sparse path: -1 auto, 0 pair-index sort, 1 LDS tile combine + sort, 2 key intervals
+    int combine = -1;        // sparse path: -1 auto, 0 pair-index sort, 1 LDS tile combine + sort, 2 key intervals,
+                             // 3 output-key work items (one scatter, in-LDS sort per work item)
     int allow_dense = 1;     // permit the degree-box path
     int digits = -1;         // radix digit schedule: -1 auto, RADIX_DIGITS_GREEDY, RADIX_DIGITS_BALANCED
     double dense_ratio = 2;  // dense when box * dense_ratio <= na * nb
@@ -76,6 +77,13 @@ struct Plan {
     int64_t iv_items = 0, iv_maxrows = 0, iv_nsamp = 0, iv_nspl = 0;
     int iv_grid = 1;
     int vsize = 4;      // payload bytes of a sort item
+    // output-key work items (SEG_BKT)
+    int nbk = 0;
+    std::vector<int64_t> bk_tile_pre, bk_sb_pre;
+    std::vector<int32_t> bk_seg;
+    int64_t bk_ntiles = 0, bk_nsb = 0, bk_nbins = 0, bk_wi_bound = 0, bk_nstage = 0, bk_fat_cap = 0;
+    size_t o_bk_hist = 0, o_bk_wbin = 0, o_bk_sbtot = 0, o_bk_sbwi = 0, o_bk_sbtb = 0, o_bk_sbpre = 0;
+    size_t o_bk_tlist = 0, o_bk_tcnt = 0, o_bk_rkey = 0, o_bk_u = 0, o_bk_opre = 0, o_bk_wi = 0, o_bk_fill = 0, o_bk_fatc = 0, o_bk_fbase = 0, o_bk_fatfill = 0, o_bk_stage = 0, o_bk_tile_pre = 0, o_bk_seg = 0, o_bk_sb_pre = 0;
     int64_t nstage = 0, nbox = 0, nck = 0;
     int nsparse = 0, ndense = 0;
     // workspace layout

@@ -46,7 +46,8 @@ def test_bad_arguments_rejected_on_host(L):
     h = pm.pm_poly(4, None, None, None)       # null n_out
     assert L.pm_mul(ctypes.byref(good), ctypes.byref(g), ctypes.byref(g), ctypes.byref(h), None, 0, None) == pm.PM_EINVAL
     assert L.pm_set_tuning(5, 0, 1) == pm.PM_EINVAL
-    assert L.pm_set_tuning(-1, 3, 1) == pm.PM_EINVAL
+    assert L.pm_set_tuning(-1, 4, 1) == pm.PM_EINVAL
+    assert L.pm_set_tuning(-1, 3, 1) == pm.PM_OK
     assert L.pm_set_tuning(-1, 2, 1) == pm.PM_OK
     assert L.pm_set_tuning(-1, -1, 1) == pm.PM_OK
     assert L.pm_set_radix(2) == pm.PM_EINVAL
