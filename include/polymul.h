@@ -190,6 +190,28 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
                        const uint64_t *stats, int64_t *max_terms, int64_t *workspace_bytes);
 
 /*
+ * Host-only helpers of the output-key interval split (Section 5, Fig. 2;
+ * Section 2's intervals), computing what the interval path's sampling and
+ * splitting kernels compute on the device.  No GPU access.
+ *
+ * pm_ival_grid: the (l+1)^2 grid samples over an na x nb pp-matrix, sample
+ *   t = r*(l+1) + c at row rows[t] = r*floor(na/l) and column cols[t] =
+ *   c*floor(nb/l) + (r odd ? floor(nb/(2l)) : 0), both clamped to the matrix
+ *   (l = 0: the single sample (0, 0)).  rows and cols: caller-owned host
+ *   arrays of (l+1)^2 entries.  PM_EINVAL unless na, nb >= 1, 0 <= l <= 63.
+ * pm_ival_splitters: for ascending packed key arrays fkeys[na], gkeys[nb]
+ *   (host memory; sums must not overflow the key fields), the splitters
+ *   S_0 < S_1 < ... < S_{n-1}: S_0 = fkeys[0] + gkeys[0], then the distinct
+ *   grid-sample sums strictly between S_0 and the end key, then the end key
+ *   fkeys[na-1] + gkeys[nb-1] + 1.  The half-open intervals [S_k, S_{k+1})
+ *   hold every exponent sum fkeys[i] + gkeys[j] exactly once.  spl:
+ *   caller-owned host array of (l+1)^2 + 2 entries; *nspl receives n.
+ */
+int pm_ival_grid(int64_t na, int64_t nb, int32_t l, int64_t *rows, int64_t *cols);
+int pm_ival_splitters(const uint64_t *fkeys, int64_t na, const uint64_t *gkeys, int64_t nb, int32_t l,
+                      uint64_t *spl, int64_t *nspl);
+
+/*
  * Process-wide tuning of later calls (the autotuner's knobs):
  *   tile_cfg     -1 automatic, else 0: 32x64, 1: 64x64, 2: 128x128 term tiles
  *                (LDS tile combine and dense path)
@@ -198,9 +220,15 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
  *                combine f-block x g-block tiles in LDS and sort the combined
  *                (monomial, coefficient) pairs; 2: output-key intervals (grid
  *                sample of the pp-matrix, per-interval merge in LDS, no global
- *                sort; products whose degree box has fewer than 2^32 cells)
+ *                sort; products whose degree box has fewer than 2^32 cells);
+ *                3: output-key work items (pairs counted into fine key bins,
+ *                bins cut into work items of at most 8192 pairs, pair indices
+ *                scattered once to their work items, each work item summed
+ *                in LDS; products with fewer than 2^32 cells and pairs).
+ *                Automatic selection takes 3 where it applies.
  *   allow_dense  0: never use the degree-box path
- * Results do not depend on these settings (FP64 always sorts pair indices).
+ * Results do not depend on these settings (FP64 sums every monomial's
+ * products in row-major order on every path).
  */
 int pm_set_tuning(int32_t tile_cfg, int32_t combine, int32_t allow_dense);
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -487,6 +488,34 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
     if (max_terms)
         for (int64_t q = 0; q < count; q++) max_terms[q] = P.bound[q];
     if (workspace_bytes) *workspace_bytes = (int64_t)P.total;
+    return PM_OK;
+}
+
+int pm_ival_grid(int64_t na, int64_t nb, int32_t l, int64_t *rows, int64_t *cols) {
+    if (na < 1 || nb < 1 || l < 0 || l > 63 || !rows || !cols) return PM_EINVAL;
+    const int64_t ns = (int64_t)(l + 1) * (l + 1);
+    for (int64_t t = 0; t < ns; t++) ival_grid_point(na, nb, l, t, rows[t], cols[t]);
+    return PM_OK;
+}
+
+int pm_ival_splitters(const uint64_t *fkeys, int64_t na, const uint64_t *gkeys, int64_t nb, int32_t l,
+                      uint64_t *spl, int64_t *nspl) {
+    if (na < 1 || nb < 1 || l < 0 || l > 63 || !fkeys || !gkeys || !spl || !nspl) return PM_EINVAL;
+    const int64_t ns = (int64_t)(l + 1) * (l + 1);
+    std::vector<uint64_t> v(ns);
+    for (int64_t t = 0; t < ns; t++) {
+        int64_t i, j;
+        ival_grid_point(na, nb, l, t, i, j);
+        v[t] = fkeys[i] + gkeys[j];
+    }
+    std::sort(v.begin(), v.end());
+    const uint64_t kmin = fkeys[0] + gkeys[0], kend = fkeys[na - 1] + gkeys[nb - 1] + 1;
+    int64_t n = 0;
+    spl[n++] = kmin;
+    for (int64_t t = 0; t < ns; t++)
+        if (v[t] > kmin && v[t] < kend && (t == 0 || v[t - 1] != v[t])) spl[n++] = v[t];
+    spl[n++] = kend;
+    *nspl = n;
     return PM_OK;
 }
 

@@ -480,4 +480,18 @@ __device__ inline u64 decompress(K ck, const VarParam *vp, int nvars, u64 lo_key
     return key;
 }
 
+// Grid sample t of Section 5 over an na x nb pp-matrix with parameter l
+// ((l + 1)^2 samples, Fig. 2 with l = 8 has 81): sample row r = t / (l + 1)
+// lies at row r * floor(na / l); its column c = t % (l + 1) lies at
+// c * floor(nb / l), shifted by floor(nb / (2 l)) on odd sample rows (the
+// staggered grid); both clamped to the matrix.  l = 0 is the single sample
+// (0, 0).  Shared by the sampling kernel and the host helper pm_ival_grid.
+__host__ __device__ inline void ival_grid_point(i64 na, i64 nb, i64 l, i64 t, i64 &i, i64 &j) {
+    const i64 r = t / (l + 1), c = t % (l + 1);
+    const i64 di = l ? na / l : 0, dj = l ? nb / l : 0, st = l ? nb / (2 * l) : 0;
+    const i64 ri = r * di, cj = (r & 1) * st + c * dj;
+    i = ri < na - 1 ? ri : na - 1;
+    j = cj < nb - 1 ? cj : nb - 1;
+}
+
 }  // namespace pm

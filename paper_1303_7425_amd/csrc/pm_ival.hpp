@@ -44,8 +44,7 @@ __device__ inline u32 lower_bound_dev(const K *a, u32 n, K x) {
     return lo;
 }
 
-// Grid samples of Section 5: rows r * floor(na / l), columns starting at a
-// row-dependent stagger of floor(nb / (2l)) and stepping floor(nb / l).
+// Grid samples of Section 5 (ival_grid_point), one exponent sum each.
 template <typename K>
 __global__ __launch_bounds__(NTHREADS) void k_ival_sample(Ctx C) {
     const int q = blockIdx.y;
@@ -55,11 +54,9 @@ __global__ __launch_bounds__(NTHREADS) void k_ival_sample(Ctx C) {
     const i64 ns = (l + 1) * (l + 1);
     const K *ck = (const K *)C.ck;
     K *samp = (K *)C.iv_samp + s.iv_samp_off;
-    const i64 di = l ? s.na / l : 0, dj = l ? s.nb / l : 0, st = l ? s.nb / (2 * l) : 0;
     for (i64 t = (i64)blockIdx.x * NTHREADS + threadIdx.x; t < ns; t += (i64)gridDim.x * NTHREADS) {
-        const i64 r = t / (l + 1), c = t % (l + 1);
-        const i64 i = min(r * di, s.na - 1);
-        const i64 j = min((r & 1) * st + c * dj, s.nb - 1);
+        i64 i, j;
+        ival_grid_point(s.na, s.nb, l, t, i, j);
         samp[t] = ck[s.ck_f + i] + ck[s.ck_g + j];
     }
 }

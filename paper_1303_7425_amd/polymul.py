@@ -88,6 +88,9 @@ def lib():
                                   ctypes.POINTER(pm_poly), vp, i64, vp, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.pm_set_radix.argtypes = [ctypes.c_int32]
+        L.pm_ival_grid.argtypes = [i64, i64, ctypes.c_int32, i64p, i64p]
+        L.pm_ival_splitters.argtypes = [ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(ctypes.c_uint64), i64,
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), i64p]
         if hasattr(L, "pm_server_create"):
             L.pm_server_create.restype = vp
             L.pm_server_create.argtypes = [i64, ctypes.c_int32]
@@ -355,7 +358,8 @@ def profile_read():
 
 def set_tuning(tile_cfg: int = -1, combine: int = -1, allow_dense: bool = True):
     """Autotuner knobs (results never depend on them): tile shape index,
-    combine (-1 auto, 0 pair-index sort, 1 LDS tile combine), dense path on/off."""
+    combine (-1 auto, 0 pair-index sort, 1 LDS tile combine, 2 output-key
+    intervals, 3 output-key work items), dense path on/off."""
     _check(lib().pm_set_tuning(tile_cfg, int(combine), int(allow_dense)), "pm_set_tuning")
 
 
@@ -371,6 +375,29 @@ def plan_from_stats(layout, na, nb, stats):
     rc = lib().pm_plan_from_stats(ctypes.byref(L), count, na_a, nb_a,
                                   st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), mt, ctypes.byref(wb))
     return rc, [int(mt[i]) for i in range(count)], int(wb.value)
+
+
+def ival_grid(na: int, nb: int, l: int):
+    """Grid samples of the interval split (host only): (rows, cols), (l+1)^2 each."""
+    ns = (l + 1) * (l + 1)
+    rows = np.zeros(max(ns, 1), np.int64)
+    cols = np.zeros(max(ns, 1), np.int64)
+    p = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().pm_ival_grid(int(na), int(nb), int(l), rows.ctypes.data_as(p), cols.ctypes.data_as(p)),
+           "pm_ival_grid")
+    return rows[:ns], cols[:ns]
+
+
+def ival_splitters(fkeys, gkeys, l: int):
+    """Splitters S_0 < ... < S_{n-1} of the interval split (host only)."""
+    fk = np.ascontiguousarray(fkeys, dtype=np.uint64)
+    gk = np.ascontiguousarray(gkeys, dtype=np.uint64)
+    out = np.zeros((l + 1) * (l + 1) + 2, np.uint64)
+    n = ctypes.c_int64(0)
+    u = ctypes.POINTER(ctypes.c_uint64)
+    _check(lib().pm_ival_splitters(fk.ctypes.data_as(u), len(fk), gk.ctypes.data_as(u), len(gk), int(l),
+                                   out.ctypes.data_as(u), ctypes.byref(n)), "pm_ival_splitters")
+    return out[:n.value]
 
 
 def autotune(layout, f: DevPoly, g: DevPoly, workspace: Workspace | None = None, stream=None):
