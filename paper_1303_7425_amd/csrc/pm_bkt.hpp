@@ -647,17 +647,26 @@ __device__ inline u32 br_excl_scan(u32 v, u32 *scratch, u32 &total, const Thr &h
 //     a_i b_j (held in registers until then) overlay the keys (cval)
 //   rounds of a work item over BK_CAP pairs: the round's items (key, pair
 //     index) are staged through stk / stx
+//   ranked accumulation (exact rings, key span <= BR_RANK_SPAN): a presence
+//     bitmap over the span gives every present key its rank among the
+//     present keys (prefix of per-word popcounts); acc[rank] accumulates and
+//     rkey[rank] holds the key, so cell order is again key order
 template <bool F64>
 struct BrLds {
     static constexpr int LK = 0, IK = 32 << 10;
     static constexpr int PERM = F64 ? (64 << 10) : (32 << 10);
     static constexpr int CNT = PERM + (16 << 10);               // [BR_NW][256] u32
     static constexpr int LKS = CNT + BR_NW * 256 * 4;           // FP64: sorted keys
-    static constexpr int BYTES = F64 ? LKS + (32 << 10) : (64 << 10);
+    static constexpr int RKEY = 64 << 10;                       // exact rings: u32[BK_CAP]
+    static constexpr int BM = RKEY + (32 << 10);                // u64[BR_RANK_SPAN / 64]
+    static constexpr int PRE = BM + (32 << 10);                 // u16[BR_RANK_SPAN / 64]
+    static constexpr int BYTES = F64 ? LKS + (32 << 10) : PRE + (8 << 10);
     static_assert(F64 || CNT + BR_NW * 256 * 4 <= (64 << 10), "exact-ring sort arrays fit under the products");
 };
 constexpr int BK_DIRECT = 8192;  // cells of the direct accumulator (64 KB)
+constexpr u32 BR_RANK_SPAN = 1u << 18;  // key span of the presence bitmap (32 KB)
 static_assert(BK_DIRECT == BR_T * BR_IPT, "each thread owns BR_IPT accumulator cells");
+static_assert(BR_RANK_SPAN / 64 == BR_T * 4, "each thread scans four bitmap words");
 
 template <int RING>
 struct BrCtx {
@@ -672,6 +681,9 @@ struct BrCtx {
     __device__ u64 *acc() { return (u64 *)mem; }
     __device__ u32 *stk() { return (u32 *)mem; }
     __device__ u32 *stx() { return (u32 *)(mem + (32 << 10)); }
+    __device__ u32 *rkey() { return (u32 *)(mem + BrLds<F64>::RKEY); }
+    __device__ u64 *bm() { return (u64 *)(mem + BrLds<F64>::BM); }
+    __device__ unsigned short *pre() { return (unsigned short *)(mem + BrLds<F64>::PRE); }
 };
 
 // Sequence position of register slot k in the striped layout.
@@ -970,6 +982,7 @@ __global__ __launch_bounds__(BR_T) __attribute__((amdgpu_waves_per_eu(4))) void 
             const u32 rbase = kbase + (u32)lo;  // smallest key of the round
             const u32 kbits = bitlen64(hi - lo - 1);
             const bool direct = !F64 && hi - lo <= (u64)BK_DIRECT;
+            const bool ranked = !F64 && !direct && hi - lo <= (u64)BR_RANK_SPAN;
             // load: register slot k holds the item at load position br_seq(k)
             u32 ks[BR_IPT], xs[BR_IPT];
 #pragma unroll
@@ -1006,27 +1019,77 @@ __global__ __launch_bounds__(BR_T) __attribute__((amdgpu_waves_per_eu(4))) void 
             u32 kk[BR_IPT];
             u64 val[BR_IPT];
             u32 em = 0;
-            if (direct) {
+            if (direct || ranked) {
                 if constexpr (!F64) {
+                    // cells in key order: the local key itself (direct) or its
+                    // rank among the round's present keys (ranked)
                     u64 *cell = B.acc();
+                    u32 *rkey = B.rkey();
+                    u64 *bm = B.bm();
+                    unsigned short *pre = B.pre();
+                    const u32 nw = ranked ? (u32)((hi - lo + 63) >> 6) : 0;
 #pragma unroll
                     for (int k = 0; k < BR_IPT; k++) cell[k * BR_T + tid] = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        if ((u32)e * BR_T + tid < nw) bm[e * BR_T + tid] = 0;
                     __syncthreads();
+                    u32 ncell = BK_DIRECT;
+                    if (ranked) {
+#pragma unroll
+                        for (int k = 0; k < BR_IPT; k++) {
+                            if (br_seq(k, h) < m) {
+                                const u32 kl = ks[k] - rbase;
+                                atomicOr((unsigned long long *)&bm[kl >> 6], 1ull << (kl & 63));
+                            }
+                        }
+                        __syncthreads();
+                        // rank of a word's first key: prefix of the popcounts
+                        // (thread t: words 4t .. 4t + 3)
+                        u32 pc[4], sum = 0;
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            const u32 wd = tid * 4 + e;
+                            pc[e] = wd < nw ? (u32)__popcll(bm[wd]) : 0u;
+                            sum += pc[e];
+                        }
+                        u32 ex = br_excl_scan(sum, s_scan, ncell, h);
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            const u32 wd = tid * 4 + e;
+                            if (wd < nw) pre[wd] = (unsigned short)ex;
+                            ex += pc[e];
+                        }
+                        __syncthreads();
+                    }
 #pragma unroll
                     for (int k = 0; k < BR_IPT; k++) {
                         if (br_seq(k, h) < m) {
+                            const u32 kl = ks[k] - rbase;
+                            u32 c = kl;
+                            if (ranked) {
+                                const u32 wd = kl >> 6;
+                                c = pre[wd] + (u32)__popcll(bm[wd] & ((1ull << (kl & 63)) - 1));
+                                rkey[c] = kl;
+                            }
                             u32 row;
-                            ring_atomic_acc<RING>(cell + (ks[k] - rbase), product(k, row));
+                            ring_atomic_acc<RING>(cell + c, product(k, row));
                         }
                         if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
                     }
                     __syncthreads();
+                    // striped read-back: slot k of a wave's lanes is the run of
+                    // cells br_seq(k, .), so a wave's cells are contiguous
 #pragma unroll
                     for (int k = 0; k < BR_IPT; k++) {
-                        const u32 c = tid * BR_IPT + k;
+                        const u32 c = br_seq(k, h);
                         kk[k] = c;
-                        val[k] = ring_cell_final<RING>(cell[c]);
-                        if (!ring_is_zero<RING>(val[k])) em |= 1u << k;
+                        val[k] = 0;
+                        if (c < ncell) {
+                            if (ranked) kk[k] = rkey[c];
+                            val[k] = ring_cell_final<RING>(cell[c]);
+                            if (!ring_is_zero<RING>(val[k])) em |= 1u << k;
+                        }
                     }
                 }
             } else {
@@ -1132,18 +1195,48 @@ __global__ __launch_bounds__(BR_T) __attribute__((amdgpu_waves_per_eu(4))) void 
                     }
                 }
             }
-            u32 u;
-            const u32 rb = br_excl_scan((u32)__popc(em), s_scan, u, h);
             // result terms: keys to bk_rkey, coefficients to the work item's
             // own staging range (its pairs are all loaded) or to bk_fatc
-            u64 at = acc + rb;
+            u32 u;
+            if (direct || ranked) {
+                // striped: wave-local ranks by ballot, then the waves' prefix
+                u32 rk[BR_IPT], before = 0;
 #pragma unroll
-            for (int k = 0; k < BR_IPT; k++) {
-                if ((em >> k) & 1) {
-                    C.bk_rkey[W.off + at] = rbase + kk[k];
-                    if (!fat) C.bk_stage[W.off + at] = val[k];
-                    else if (fbase != ~0ull) C.bk_fatc[fbase + at] = val[k];
-                    at++;
+                for (int k = 0; k < BR_IPT; k++) {
+                    const u64 bal = __ballot((em >> k) & 1u);
+                    rk[k] = before + mbcnt(bal);
+                    before += (u32)__popcll(bal);
+                }
+                if (h.lane == 0) s_scan[h.w] = before;
+                __syncthreads();
+                u32 wpre = 0, tot = 0;
+#pragma unroll
+                for (u32 i = 0; i < (u32)BR_NW; i++) {
+                    const u32 v = s_scan[i];
+                    if (i < h.w) wpre += v;
+                    tot += v;
+                }
+                u = tot;
+#pragma unroll
+                for (int k = 0; k < BR_IPT; k++) {
+                    if ((em >> k) & 1) {
+                        const u64 at = acc + wpre + rk[k];
+                        C.bk_rkey[W.off + at] = rbase + kk[k];
+                        if (!fat) C.bk_stage[W.off + at] = val[k];
+                        else if (fbase != ~0ull) C.bk_fatc[fbase + at] = val[k];
+                    }
+                }
+            } else {
+                const u32 rb = br_excl_scan((u32)__popc(em), s_scan, u, h);
+                u64 at = acc + rb;
+#pragma unroll
+                for (int k = 0; k < BR_IPT; k++) {
+                    if ((em >> k) & 1) {
+                        C.bk_rkey[W.off + at] = rbase + kk[k];
+                        if (!fat) C.bk_stage[W.off + at] = val[k];
+                        else if (fbase != ~0ull) C.bk_fatc[fbase + at] = val[k];
+                        at++;
+                    }
                 }
             }
             acc += u;

@@ -1741,8 +1741,8 @@ static void launch_bkt(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
     }
     {
         ProfScope ps("bk_reduce", st);
-        // resident workgroups per CU: LDS allows two for the exact rings (about 72 KB each), one for FP64
-        const int per_cu = RING == RING_F64 ? 1 : std::max(1, 1024 / BR_T);
+        // one resident workgroup per CU: 1024 threads and 140-150 KB of LDS
+        const int per_cu = 1;
         hipLaunchKernelGGL((k_bk_reduce<RING>), dim3(grid_for(P.bk_wi_bound, cus * per_cu)), dim3(BR_T), 0, st, C);
     }
     ProfScope ps("bk_place", st);
