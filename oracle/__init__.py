@@ -22,8 +22,9 @@ SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 OK, EINVAL, EUNSORTED, EOVERFLOW, ERANGE, ECAPACITY, ENOMEM, EINT64 = 0, -1, -2, -3, -4, -5, -6, -9
-RING_CODE = {"modp": 0, "f64": 1, "i64": 2}
-COEF_DTYPE = {"modp": np.uint64, "f64": np.float64, "i64": np.int64}
+RING_CODE = {"modp": 0, "f64": 1, "i64": 2, "modq": 3, "z192": 4}
+COEF_DTYPE = {"modp": np.uint64, "f64": np.float64, "i64": np.int64, "modq": np.uint64, "z192": np.uint64}
+COEF_WORDS = {"z192": 3}    # coefficient words per term (1 for the other rings)
 
 _lib = None
 
@@ -95,7 +96,8 @@ def mul_arrays(nvars, bits, ring, fk, fc, gk, gc, cap=None):
             raise OracleError(rc)
         cap = int(b.value)
     hk = np.zeros(max(cap, 1), dtype=np.uint64)
-    hc = np.zeros(max(cap, 1), dtype=COEF_DTYPE[ring])
+    w = COEF_WORDS.get(ring, 1)
+    hc = np.zeros((max(cap, 1), w) if w > 1 else max(cap, 1), dtype=COEF_DTYPE[ring])
     ha = np.zeros(max(cap, 1), dtype=np.float64) if ring == "f64" else None
     rc = L.oracle_mul(nvars, bits, RING_CODE[ring], fk.size, pfk, pfc, gk.size, pgk, pgc,
                       cap, hk.ctypes.data, hc.ctypes.data, ha.ctypes.data if ha is not None else None,

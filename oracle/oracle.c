@@ -29,7 +29,14 @@
  *   ring 2  int64; exact sums in a three-word (192-bit) signed accumulator,
  *           mirroring the three-word accumulator of the paper's benchmark
  *           section; a result that does not fit int64 is reported.
- * Only an exact +/-0.0 (ring 1) or 0 (rings 0, 2) is dropped.
+ *   ring 3  integers mod q = 2^64 - 59 (a prime); residues in [0, q);
+ *           products and sums reduced with a 128-bit remainder.
+ *   ring 4  integers as three-word (192-bit) two's-complement values, all
+ *           arithmetic modulo 2^192: operands, products and sums wrap.  The
+ *           result is the exact integer product whenever every output
+ *           coefficient lies in [-2^191, 2^191).  Coefficient arrays hold
+ *           three words per term, least significant first.
+ * Only an exact +/-0.0 (ring 1) or 0 (rings 0, 2, 3, 4) is dropped.
  *
  * Build: gcc -O2 -ffp-contract=off -shared -fPIC oracle.c -o liboracle.so
  */
@@ -50,8 +57,11 @@
 #define OR_MODP 0
 #define OR_F64 1
 #define OR_I64 2
+#define OR_MODQ 3
+#define OR_Z192 4
 
 static const uint64_t P61 = (((uint64_t)1) << 61) - 1;
+static const uint64_t Q64 = ~(uint64_t)0 - 58; /* 2^64 - 59 */
 
 /* Three-word two's-complement accumulator (w[0] least significant). */
 typedef struct { uint64_t w[3]; } acc192;
@@ -73,6 +83,29 @@ static void acc192_add_i128(acc192 *a, __int128 v) {
 
 static int acc192_is_zero(const acc192 *a) { return (a->w[0] | a->w[1] | a->w[2]) == 0; }
 
+/* a += b (mod 2^192). */
+static void acc192_add(acc192 *a, const acc192 *b) {
+    unsigned __int128 t = (unsigned __int128)a->w[0] + b->w[0];
+    a->w[0] = (uint64_t)t;
+    t = (t >> 64) + a->w[1] + b->w[1];
+    a->w[1] = (uint64_t)t;
+    a->w[2] = (uint64_t)(t >> 64) + a->w[2] + b->w[2];
+}
+
+/* a * b (mod 2^192): schoolbook over 64-bit words, dropping every partial
+   product of weight 2^192 or more.  Two's-complement operands need no
+   special case, since the product is taken modulo 2^192. */
+static acc192 acc192_mul(const uint64_t *a, const uint64_t *b) {
+    acc192 r;
+    unsigned __int128 t = (unsigned __int128)a[0] * b[0];
+    r.w[0] = (uint64_t)t;
+    unsigned __int128 u = (t >> 64) + (unsigned __int128)a[0] * b[1];
+    unsigned __int128 v = (unsigned __int128)(uint64_t)u + (unsigned __int128)a[1] * b[0];
+    r.w[1] = (uint64_t)v;
+    r.w[2] = (uint64_t)(u >> 64) + (uint64_t)(v >> 64) + a[0] * b[2] + a[1] * b[1] + a[2] * b[0];
+    return r;
+}
+
 /* Returns 1 and stores the value when the accumulator fits int64. */
 static int acc192_to_i64(const acc192 *a, int64_t *out) {
     int64_t v = (int64_t)a->w[0];
@@ -84,8 +117,8 @@ static int acc192_to_i64(const acc192 *a, int64_t *out) {
 
 typedef struct {
     uint64_t key;
-    uint64_t modp;   /* ring 0 */
-    acc192 exact;    /* ring 2 */
+    uint64_t modp;   /* rings 0 and 3 */
+    acc192 exact;    /* rings 2 and 4 */
     double sum;      /* ring 1 */
     double abssum;   /* ring 1 */
 } entry;
@@ -158,7 +191,7 @@ static int table_grow(table *t) {
 int oracle_validate(int nvars, int bits, int ring, int64_t na, const uint64_t *fk, const void *fc,
                     int64_t nb, const uint64_t *gk, const void *gc) {
     if (nvars < 1 || bits < 1 || nvars * bits > 64) return OR_EINVAL;
-    if (ring != OR_MODP && ring != OR_F64 && ring != OR_I64) return OR_EINVAL;
+    if (ring != OR_MODP && ring != OR_F64 && ring != OR_I64 && ring != OR_MODQ && ring != OR_Z192) return OR_EINVAL;
     if (na < 0 || nb < 0) return OR_EINVAL;
     if ((na > 0 && (!fk || !fc)) || (nb > 0 && (!gk || !gc))) return OR_EINVAL;
     int used = nvars * bits;
@@ -178,6 +211,7 @@ int oracle_validate(int nvars, int bits, int ring, int64_t na, const uint64_t *f
                 if (e > mx[v]) mx[v] = e;
             }
             if (ring == OR_MODP && ((const uint64_t *)c)[i] >= P61) return OR_ERANGE;
+            if (ring == OR_MODQ && ((const uint64_t *)c)[i] >= Q64) return OR_ERANGE;
             if (ring == OR_F64 && !isfinite(((const double *)c)[i])) return OR_ERANGE;
         }
     }
@@ -229,6 +263,13 @@ int oracle_mul(int nvars, int bits, int ring, int64_t na, const uint64_t *fk, co
             } else if (ring == OR_I64) {
                 int64_t a = ((const int64_t *)fc)[i], b = ((const int64_t *)gc)[j];
                 acc192_add_i128(&e->exact, (__int128)a * b);
+            } else if (ring == OR_MODQ) {
+                uint64_t a = ((const uint64_t *)fc)[i], b = ((const uint64_t *)gc)[j];
+                uint64_t c = (uint64_t)(((unsigned __int128)a * b) % Q64);
+                e->modp = (uint64_t)(((unsigned __int128)e->modp + c) % Q64);
+            } else if (ring == OR_Z192) {
+                acc192 c = acc192_mul((const uint64_t *)fc + 3 * i, (const uint64_t *)gc + 3 * j);
+                acc192_add(&e->exact, &c);
             } else {
                 double a = ((const double *)fc)[i], b = ((const double *)gc)[j];
                 volatile double c = a * b; /* rounded once, never fused with the add */
@@ -247,8 +288,9 @@ int oracle_mul(int nvars, int bits, int ring, int64_t na, const uint64_t *fk, co
     for (uint64_t s = 0; s < t.cap; s++) {
         if (!t.used[s]) continue;
         const entry *e = &t.e[s];
-        int zero = (ring == OR_MODP) ? (e->modp == 0) : (ring == OR_I64) ? acc192_is_zero(&e->exact)
-                                                                         : (e->sum == 0.0);
+        int zero = (ring == OR_MODP || ring == OR_MODQ) ? (e->modp == 0)
+                   : (ring == OR_I64 || ring == OR_Z192)  ? acc192_is_zero(&e->exact)
+                                                          : (e->sum == 0.0);
         if (!zero) out[m++] = *e;
     }
     table_free(&t);
@@ -260,8 +302,10 @@ int oracle_mul(int nvars, int bits, int ring, int64_t na, const uint64_t *fk, co
     }
     for (uint64_t s = 0; s < m; s++) {
         hk[s] = out[s].key;
-        if (ring == OR_MODP) {
+        if (ring == OR_MODP || ring == OR_MODQ) {
             ((uint64_t *)hc)[s] = out[s].modp;
+        } else if (ring == OR_Z192) {
+            for (int k = 0; k < 3; k++) ((uint64_t *)hc)[3 * s + k] = out[s].exact.w[k];
         } else if (ring == OR_I64) {
             int64_t v;
             if (!acc192_to_i64(&out[s].exact, &v)) {

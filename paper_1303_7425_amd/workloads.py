@@ -29,11 +29,14 @@ from dataclasses import dataclass, field
 import numpy as np
 
 P61 = (1 << 61) - 1
+Q64 = (1 << 64) - 59
 
 RING_MODP = "modp"
 RING_F64 = "f64"
 RING_I64 = "i64"
-RINGS = (RING_MODP, RING_F64, RING_I64)
+RING_MODQ = "modq"      # integers mod the prime 2^64 - 59
+RING_Z192 = "z192"      # integers as three-word two's-complement values (least significant word first)
+RINGS = (RING_MODP, RING_F64, RING_I64, RING_MODQ, RING_Z192)
 
 
 @dataclass
@@ -96,7 +99,34 @@ def to_ring(values, ring: str) -> np.ndarray:
         return np.array([int(v) for v in values], dtype=np.int64)
     if ring == RING_F64:
         return np.array([float(v) for v in values], dtype=np.float64)
+    if ring == RING_MODQ:
+        return np.array([int(v) % Q64 for v in values], dtype=np.uint64)
+    if ring == RING_Z192:
+        return z192_words(values)
     raise ValueError(ring)
+
+
+def z192_words(values) -> np.ndarray:
+    """Exact integers in [-2^191, 2^191) -> (n, 3) uint64 words of their
+    two's-complement form, least significant first."""
+    out = np.zeros((len(values), 3), dtype=np.uint64)
+    m = (1 << 64) - 1
+    for i, v in enumerate(values):
+        v = int(v)
+        if not (-(1 << 191) <= v < (1 << 191)):
+            raise OverflowError("coefficient does not fit 192 bits")
+        u = v % (1 << 192)
+        out[i] = (u & m, (u >> 64) & m, u >> 128)
+    return out
+
+
+def z192_ints(words: np.ndarray) -> list:
+    """(n, 3) uint64 two's-complement words -> exact Python integers."""
+    out = []
+    for w0, w1, w2 in np.asarray(words, dtype=np.uint64).reshape(-1, 3).tolist():
+        u = int(w0) | (int(w1) << 64) | (int(w2) << 128)
+        out.append(u - (1 << 192) if u >> 191 else u)
+    return out
 
 
 def _compositions(n: int, m: int):
@@ -219,13 +249,34 @@ def residues(rng: np.random.Generator, n: int) -> np.ndarray:
     return rng.integers(1, P61, size=n, dtype=np.uint64)
 
 
-def with_random_coefs(p: Poly, rng: np.random.Generator, ring: str) -> Poly:
+def big_signed(rng: np.random.Generator, n: int, bits: int) -> list:
+    """Exact integers uniform in (-2^bits, 2^bits), zero redrawn."""
+    out = []
+    while len(out) < n:
+        w = rng.integers(0, 1 << 62, size=(n - len(out), (bits + 61) // 62 + 1), dtype=np.int64).tolist()
+        for row in w:
+            v = 0
+            for x in row[1:]:
+                v = (v << 62) | int(x)
+            v &= (1 << bits) - 1
+            if v:
+                out.append(-v if row[0] & 1 else v)
+    return out
+
+
+def with_random_coefs(p: Poly, rng: np.random.Generator, ring: str, bits: int = 80) -> Poly:
+    """Fresh random coefficients; for z192 exact integers of up to `bits` bits."""
     lay = Layout(p.layout.nvars, p.layout.bits, ring)
     n = len(p)
     if ring == RING_F64:
         c = uniform_pm1(rng, n)
     elif ring == RING_MODP:
         c = residues(rng, n)
+    elif ring == RING_MODQ:
+        c = rng.integers(1, Q64, size=n, dtype=np.uint64)
+    elif ring == RING_Z192:
+        ex = big_signed(rng, n, bits)
+        return Poly(lay, p.keys.copy(), z192_words(ex), ex)
     else:
         c = rng.integers(-(1 << 20), (1 << 20) + 1, size=n, dtype=np.int64)
     return Poly(lay, p.keys.copy(), c)
@@ -249,6 +300,11 @@ def random_sparse(rng: np.random.Generator, n: int, nvars: int = 6, bits: int = 
         c = uniform_pm1(rng, n)
     elif ring == RING_MODP:
         c = residues(rng, n)
+    elif ring == RING_MODQ:
+        c = rng.integers(1, Q64, size=n, dtype=np.uint64)
+    elif ring == RING_Z192:
+        ex = big_signed(rng, n, 80)
+        return Poly(lay, keys, z192_words(ex), ex)
     else:
         c = rng.integers(-(1 << 20), (1 << 20) + 1, size=n, dtype=np.int64)
     return Poly(lay, keys, c)
