@@ -1,0 +1,159 @@
+"""Full-size products on the GPU checked against closed forms and the oracle.
+
+  * (1+x+y+z+t)^30 * ((1+x+y+z+t)^30 + 1) mod p, the large request of the
+    serving mix: all C(64,4) = 635,376 terms against M(60; e) + M(30; e),
+    plus evaluation at 16 random points.
+  * Example 1 of the paper's benchmark section at n = 40 mod p:
+    (1+x+y+z+t)^40 * ((1+x+y+z+t)^40 + 1), 1.84e10 term products; the paper
+    reports 1,929,501 result terms, each equal to M(80; e) + M(40; e).
+  * The largest pairs of the batched workload recipe (6 variables, 10 bits,
+    exponents 0..15, log-uniform sizes in [50, 20000], seed 4), term by term
+    against the oracle.
+
+M(n; e) is the multinomial coefficient n! / (e_1! ... e_4! (n - |e|)!), the
+coefficient of x^e in (1+x+y+z+t)^n; it is reduced mod p through inverse
+factorials (p is a prime larger than n).
+"""
+import math
+import random
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle
+from paper_1303_7425_amd import workloads as W
+
+P = W.P61
+MASK31 = (1 << 31) - 1
+
+
+def mulmod_np(a, b):
+    """Elementwise a*b mod 2^61-1 on uint64 arrays of residues (31-bit limbs)."""
+    a = a.astype(np.uint64)
+    b = b.astype(np.uint64)
+    a1, a0 = a >> np.uint64(31), a & np.uint64(MASK31)
+    b1, b0 = b >> np.uint64(31), b & np.uint64(MASK31)
+    hi = a1 * b1                       # < 2^60, weight 2^62 = 2 (mod p)
+    mid = a1 * b0 + a0 * b1            # < 2^62, weight 2^31
+    lo = a0 * b0                       # < 2^62
+    m_hi, m_lo = mid >> np.uint64(30), mid & np.uint64((1 << 30) - 1)   # mid*2^31 = m_hi*2^61 + m_lo*2^31
+    x = np.uint64(2) * hi + m_hi + (m_lo << np.uint64(31))              # < 2^62
+    x = (x & np.uint64(P)) + (x >> np.uint64(61))
+    x = (x & np.uint64(P)) + (x >> np.uint64(61))
+    lo = (lo & np.uint64(P)) + (lo >> np.uint64(61))
+    x = x + lo                         # < 2^62 + 2
+    x = (x & np.uint64(P)) + (x >> np.uint64(61))
+    return np.where(x >= np.uint64(P), x - np.uint64(P), x)
+
+
+def summod_np(v):
+    v = v.astype(np.uint64)
+    s = int((v & np.uint64(0xFFFFFFFF)).sum()) + (int((v >> np.uint64(32)).sum()) << 32)
+    return s % P
+
+
+def test_mulmod_np_helper():
+    rr = random.Random(7)
+    a = [rr.randrange(P) for _ in range(2000)] + [0, 1, P - 1, P - 1]
+    b = [rr.randrange(P) for _ in range(2000)] + [P - 1, P - 1, P - 1, 1]
+    got = mulmod_np(np.array(a, np.uint64), np.array(b, np.uint64)).tolist()
+    assert got == [x * y % P for x, y in zip(a, b)]
+    assert summod_np(np.array(a, np.uint64)) == sum(a) % P
+
+
+def fact_tables(n):
+    f = [1] * (n + 1)
+    for i in range(1, n + 1):
+        f[i] = f[i - 1] * i % P
+    inv = [pow(x, P - 2, P) for x in f]
+    return np.array(f, np.uint64), np.array(inv, np.uint64)
+
+
+def multinomial_modp(n, ex, fact, inv):
+    """M(n; e) mod p for every row e of ex (|e| <= n assumed where used)."""
+    s = ex.sum(axis=1)
+    ok = s <= n
+    r = np.full(ex.shape[0], int(fact[n]), np.uint64)
+    for v in range(ex.shape[1]):
+        r = mulmod_np(r, inv[ex[:, v]])
+    r = mulmod_np(r, inv[np.where(ok, n - s, 0)])
+    return np.where(ok, r, np.uint64(0))
+
+
+def check_dense_family(n, hk, hc):
+    """h = f (f + 1) with f = (1+x+y+z+t)^n: every term M(2n; e) + M(n; e)."""
+    ex = W.unpack(hk, 4, 16).astype(np.int64)
+    fact, inv = fact_tables(2 * n)
+    want = multinomial_modp(2 * n, ex, fact, inv) + multinomial_modp(n, ex, fact, inv)
+    want = np.where(want >= np.uint64(P), want - np.uint64(P), want)
+    assert np.array_equal(hc.view(np.uint64), want)
+    return ex
+
+
+def gpu_mul(f, g):
+    from paper_1303_7425_amd import polymul as pm
+    lay = (f.layout.nvars, f.layout.bits, f.layout.ring)
+    t = time.perf_counter()
+    h = pm.mul(lay, pm.to_device(f), pm.to_device(g))
+    hk, hc = h.numpy()
+    dt = time.perf_counter() - t
+    assert pm.last_call_status() == 0
+    return hk, hc, dt
+
+
+def test_serve_large_request_n30_closed_form_and_evaluation():
+    n = 30
+    f = W.dense_power(n, 4, 16, "modp")
+    g = W.add_constant(f, 1)
+    assert len(f) == math.comb(34, 4) == 46376
+    print(f"[fullscale] (1+x+y+z+t)^{n} x (same+1) mod p, {len(f) * len(g):.3e} pairs", flush=True)
+    hk, hc, dt = gpu_mul(f, g)
+    assert hk.size == math.comb(64, 4) == 635376
+    assert np.all(hk[1:] > hk[:-1])
+    ex = check_dense_family(n, hk, hc)
+    # h(a) = f(a) (f(a) + 1) at 16 random points mod p
+    rr = random.Random(2)
+    for _ in range(16):
+        a = [rr.randrange(P) for _ in range(4)]
+        v = hc.view(np.uint64)
+        for k in range(4):
+            pw = np.array([pow(a[k], e, P) for e in range(2 * n + 1)], np.uint64)
+            v = mulmod_np(v, pw[ex[:, k]])
+        fa = pow((1 + sum(a)) % P, n, P)
+        assert summod_np(v) == fa * (fa + 1) % P
+
+
+def test_example1_n40_term_count_and_closed_form():
+    # the paper's Example 1: 1,929,501 result terms
+    n = 40
+    f = W.dense_power(n, 4, 16, "modp")
+    g = W.add_constant(f, 1)
+    assert len(f) == math.comb(44, 4) == 135751
+    print(f"[fullscale] Example 1 n={n} mod p, {len(f) * len(g):.3e} pairs", flush=True)
+    hk, hc, dt = gpu_mul(f, g)
+    print(f"[fullscale] Example 1: {hk.size} terms in {dt:.3f} s (including upload and read-back)", flush=True)
+    assert hk.size == 1929501 == math.comb(84, 4)
+    assert np.all(hk[1:] > hk[:-1])
+    check_dense_family(n, hk, hc)
+
+
+def _config4_largest(k):
+    sizes, _ = W.config4_sizes()
+    order = np.argsort(sizes[:, 0] * sizes[:, 1])[::-1]
+    return [tuple(int(x) for x in sizes[q]) for q in order[:k]]
+
+
+@pytest.mark.parametrize("rank,ring", [(0, "modp"), (1, "modp"), (0, "f64")])
+def test_config4_largest_pairs_vs_oracle(rank, ring):
+    from test_gpu_parity import assert_same
+    na, nb = _config4_largest(2)[rank]
+    rng = W.rng_for(4000 + rank)
+    f = W.random_sparse(rng, na, 6, 10, 15, ring)
+    g = W.random_sparse(rng, nb, 6, 10, 15, ring)
+    print(f"[fullscale] config-4 pair of rank {rank} by size: {na} x {nb} = {na * nb:.3e} pairs, {ring}", flush=True)
+    hk, hc, _ = gpu_mul(f, g)
+    want = oracle.mul(f, g)
+    assert_same((hk, hc), want, ring, f"cfg4 rank {rank}")
