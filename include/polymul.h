@@ -117,6 +117,23 @@ int pm_mul(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const 
            int64_t workspace_bytes, void *stream);
 
 /*
+ * pm_mul without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operands, result and error codes as pm_mul, but
+ * the workspace is a static device array of PM_NOALLOC_SCRATCH_BYTES that
+ * every device holds from library load until the process ends; the call
+ * makes no device or pinned-host allocation.  A product whose pm_mul_bound
+ * workspace exceeds that size is rejected with PM_ENOMEM before any kernel
+ * that writes h is enqueued.  All calls on one device share the array (it
+ * keeps the last call's contents; the kernels clear what must start at
+ * zero): calls whose work overlaps on one device race, so serialise them on
+ * one stream.  Like pm_mul it synchronises `stream` for the operand
+ * validation before enqueueing the product.
+ */
+#define PM_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int pm_mul_noalloc(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *stream);
+
+/*
  * Batched form: `count` independent products h[k] = f[k] * g[k] sharing one
  * layout, run from a single device work queue of tiles (persistent kernels,
  * replayed from a HIP graph).  max_terms[k] receives each product's bound;

@@ -42,7 +42,7 @@ int device_cus() {
 }
 
 HostStage::~HostStage() {
-    if (pin) (void)hipHostFree(pin);
+    if (pin && !fixed) (void)hipHostFree(pin);
     if (ev) (void)hipEventDestroy(ev);
     if (dtmp) (void)hipFree(dtmp);
 }
@@ -50,6 +50,15 @@ HostStage::~HostStage() {
 // Pinned host staging of at least `bytes`; waits until the last upload that
 // read from it has completed.
 int HostStage::reserve(size_t bytes) {
+    if (fixed) {
+        // pageable memory: an upload from it has been staged by the time
+        // hipMemcpyAsync returns, so it is free again at once
+        if (bytes > cap) {
+            set_error("host staging of the no-allocation entry point", hipErrorOutOfMemory);
+            return PM_ENOMEM;
+        }
+        return PM_OK;
+    }
     if (!ev) {
         hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -186,12 +195,12 @@ int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st) {
     if (!P.bk_seg.empty()) memcpy(pin + (P.o_bk_seg - d0), P.bk_seg.data(), 4 * P.bk_seg.size());
     if (!P.bk_sb_pre.empty()) memcpy(pin + (P.o_bk_sb_pre - d0), P.bk_sb_pre.data(), 8 * P.bk_sb_pre.size());
     hipError_t e = hipMemcpyAsync((char *)ws + d0, pin, P.r_desc.bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipEventRecord(hs.ev, st);
+    if (e == hipSuccess) e = hs.fixed ? hipStreamSynchronize(st) : hipEventRecord(hs.ev, st);
     if (e != hipSuccess) {
         set_error("descriptor upload", e);
         return PM_EDEVICE;
     }
-    hs.used = true;
+    hs.used = !hs.fixed;
     return PM_OK;
 }
 
@@ -303,6 +312,77 @@ int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, cons
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// pm_mul_noalloc: pm_mul with the workspace in a static device array.
+// ---------------------------------------------------------------------------
+// Each device that loads the library holds its own copy of `scratch` until the
+// process ends.  In host code the array's name is only a stand-in: its device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current, and only that address is passed on.  The host side stages
+// descriptors and statistics through a static pageable buffer.
+static constexpr size_t NOALLOC_SCRATCH = (size_t)PM_NOALLOC_SCRATCH_BYTES;
+static_assert(NOALLOC_SCRATCH % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH];
+
+namespace {
+constexpr size_t NOALLOC_HOST = (size_t)4 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+alignas(256) unsigned char g_noalloc_host[NOALLOC_HOST];
+void *g_scratch_addr[NOALLOC_MAX_DEVICES];
+HostStage g_noalloc_stage;
+
+// Device address of `scratch` on the current device (caller holds g_mu).
+int scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("hipGetDevice", e);
+        return PM_EDEVICE;
+    }
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("device index beyond the no-allocation table", hipErrorInvalidDevice);
+        return PM_EDEVICE;
+    }
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch)", e);
+            return PM_EDEVICE;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return PM_OK;
+}
+}  // namespace
+
+extern "C" int pm_mul_noalloc(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
+                              void *stream) {
+    int rc = check_args(layout, 1, f, g, h);
+    if (rc) return rc;
+    if (!h) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    if (!g_noalloc_stage.fixed) {
+        g_noalloc_stage.fixed = true;
+        g_noalloc_stage.pin = g_noalloc_host;
+        g_noalloc_stage.cap = NOALLOC_HOST;
+    }
+    const size_t need0 = stats_region_bytes(1, (int)layout->nvars) + sizeof(DevSeg);
+    if (need0 > NOALLOC_SCRATCH) return PM_ENOMEM;
+    Plan P;
+    rc = stats_and_plan(g_noalloc_stage, layout, 1, f, g, ws, (hipStream_t)stream, g_tune, P);
+    if (rc) return rc;
+    if (P.total > NOALLOC_SCRATCH) {
+        set_error("workspace beyond the static scratch of pm_mul_noalloc", hipErrorOutOfMemory);
+        return PM_ENOMEM;
+    }
+    return upload_and_launch(g_noalloc_stage, P, h, ws, (hipStream_t)stream);
+}
 
 struct pm_batch {
     pm::Plan plan;

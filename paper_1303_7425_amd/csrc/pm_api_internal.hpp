@@ -14,6 +14,7 @@ namespace pm {
 struct HostStage {
     void *pin = nullptr;
     size_t cap = 0;
+    bool fixed = false;  // pin is caller-provided pageable memory of cap bytes: never grown or freed, no event
     hipEvent_t ev = nullptr;
     bool used = false;
     void *dtmp = nullptr;

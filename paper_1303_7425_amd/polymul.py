@@ -88,6 +88,8 @@ def lib():
                                   ctypes.POINTER(pm_poly), vp, i64, vp, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.pm_set_radix.argtypes = [ctypes.c_int32]
+        L.pm_mul_noalloc.argtypes = [ctypes.POINTER(pm_layout), ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_cpoly),
+                                     ctypes.POINTER(pm_poly), vp]
         L.pm_ival_grid.argtypes = [i64, i64, ctypes.c_int32, i64p, i64p]
         L.pm_ival_splitters.argtypes = [ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(ctypes.c_uint64), i64,
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), i64p]
@@ -210,6 +212,27 @@ def mul(layout, f: DevPoly, g: DevPoly, out=None, workspace: Workspace | None = 
     h = pm_poly(min(hk.numel(), hc.numel()), hn.data_ptr(), hk.data_ptr(), hc.data_ptr())
     _check(lib().pm_mul(ctypes.byref(L), ctypes.byref(_cpoly(f)), ctypes.byref(_cpoly(g)), ctypes.byref(h),
                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "pm_mul")
+    n = -1
+    if sync:
+        (stream or torch.cuda.current_stream()).synchronize()
+        n = int(hn.item())
+    return DevPoly(hk, hc, n, ring)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def mul_noalloc(layout, f: DevPoly, g: DevPoly, out, stream=None, sync: bool = True):
+    """h = f * g through pm_mul_noalloc: the library uses its static device
+    scratch, so only the caller's output arrays `out` = (keys, coefs, n) are
+    passed.  Returns DevPoly (n read back when sync=True)."""
+    import torch
+    L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+    ring = {v: k for k, v in RING_CODE.items()}[L.ring]
+    hk, hc, hn = out
+    h = pm_poly(min(hk.numel(), hc.numel()), hn.data_ptr(), hk.data_ptr(), hc.data_ptr())
+    _check(lib().pm_mul_noalloc(ctypes.byref(L), ctypes.byref(_cpoly(f)), ctypes.byref(_cpoly(g)), ctypes.byref(h),
+                                _stream_ptr(stream)), "pm_mul_noalloc")
     n = -1
     if sync:
         (stream or torch.cuda.current_stream()).synchronize()
