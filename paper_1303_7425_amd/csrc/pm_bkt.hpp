@@ -249,7 +249,8 @@ __global__ __launch_bounds__(BK_T) void k_bk_count(Ctx C) {
 // ---------------------------------------------------------------------------
 // Greedy cut of one super-bin (BK_SB fine bins, four per thread) into work
 // items: a work item starting at bin b takes the following bins while their
-// pairs stay within BK_CAP (a bin over BK_CAP alone).  nxt(b) is where that
+// pairs stay within BK_CAP (a bin over BK_CAP alone) and, for exact rings, at
+// most bk_span_bins bins (a key span of BR_RANK_SPAN).  nxt(b) is where that
 // work item ends; the work-item starts are the orbit of bin 0 under nxt.  The
 // orbit is marked by pointer doubling: nxt^(2^l) for l <= BC_LV, then jumps of
 // 2^(BC_LV-1), ..., 1 from every marked bin, repeated from nxt^(2^BC_LV) of the
@@ -297,6 +298,7 @@ __global__ __launch_bounds__(BC_T) void k_bk_cut(Ctx C) {
         if (t == BC_T - 1) L.pre[BK_SB] = tot;
     }
     __syncthreads();
+    const int span_bins = C.segs[q].bk_span_bins;
     for (int k = 0; k < 4; k++) {
         const int b = 4 * t + k;
         const u32 lim = L.pre[b] + (u32)BK_CAP;  // pairs < 2^32 per product
@@ -310,6 +312,7 @@ __global__ __launch_bounds__(BC_T) void k_bk_cut(Ctx C) {
             }
             e = lo;
         }
+        if (span_bins > 0 && e > b + span_bins) e = b + span_bins;
         L.jmp[0][b] = (unsigned short)e;
         L.on[b] = 0;
     }
@@ -664,7 +667,7 @@ struct BrLds {
     static_assert(F64 || CNT + BR_NW * 256 * 4 <= (64 << 10), "exact-ring sort arrays fit under the products");
 };
 constexpr int BK_DIRECT = 8192;  // cells of the direct accumulator (64 KB)
-constexpr u32 BR_RANK_SPAN = 1u << 18;  // key span of the presence bitmap (32 KB)
+constexpr u32 BR_RANK_SPAN = 1u << BK_RANK_LOG;  // key span of the presence bitmap (32 KB)
 static_assert(BK_DIRECT == BR_T * BR_IPT, "each thread owns BR_IPT accumulator cells");
 static_assert(BR_RANK_SPAN / 64 == BR_T * 4, "each thread scans four bitmap words");
 

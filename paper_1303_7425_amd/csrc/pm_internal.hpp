@@ -38,6 +38,7 @@ constexpr int BK_SB_LOG = 12;
 constexpr int BK_SB = 1 << BK_SB_LOG;  // fine bins per super-bin (the unit of the greedy cut)
 constexpr int BK_CAP = 8192;           // pairs of a work item sorted in one LDS pass
 constexpr int BK_BIN_PAIRS = 8;        // about this many term pairs per fine bin
+constexpr int BK_RANK_LOG = 18;        // exact rings: key span (log2) a work item sums by rank in LDS
 
 // One work item: fine bins [bin_lo, bin_hi) of product q (bins local to the
 // product), its items at [off, end) of the staging array.
@@ -130,7 +131,7 @@ struct DevSeg {
     i64 *n_out;
     i64 cap;
     i32 mode;
-    i32 pad;
+    i32 bk_span_bins;              // SEG_BKT: most fine bins per work item (0: no limit)
 };
 
 // Values produced on the device during a call.

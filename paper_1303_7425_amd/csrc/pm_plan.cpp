@@ -327,6 +327,9 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             const int64_t nbins = (int64_t)((cells + (1ull << fs) - 1) >> fs);
             const int64_t nsb = (nbins + BK_SB - 1) / BK_SB;
             d.bk_fs = fs;
+            // exact rings: work items span at most 2^BK_RANK_LOG keys, so each
+            // one is summed by rank in LDS without a sort
+            d.bk_span_bins = (ring != RING_F64 && fs <= BK_RANK_LOG) ? (1 << (BK_RANK_LOG - fs)) : 0;
             d.bk_bin_off = P.bk_nbins;
             d.bk_sb_first = P.bk_nsb;
             d.bk_nsb = nsb;
@@ -346,7 +349,9 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
             P.bk_seg.push_back(q);
             // two consecutive work items of a super-bin hold more than BK_CAP
             // pairs, so a super-bin of p pairs has at most 2 ceil(p / BK_CAP) + 1
-            P.bk_wi_bound += 2 * (int64_t)((pairs + BK_CAP - 1) / BK_CAP) + 3 * nsb + 1;
+            // (or the first spans bk_span_bins bins)
+            const int64_t span_items = d.bk_span_bins ? 2 * nsb * ((BK_SB + d.bk_span_bins - 1) / d.bk_span_bins) : 0;
+            P.bk_wi_bound += 2 * (int64_t)((pairs + BK_CAP - 1) / BK_CAP) + 3 * nsb + 1 + span_items;
             P.bk_nstage += (int64_t)pairs;
             // a work item over BK_CAP pairs is one fine bin: at most 2^fs result terms
             const uint64_t fat_items = pairs / (BK_CAP + 1);
