@@ -23,6 +23,20 @@
  *             PM_F64     IEEE double, finite
  *             PM_I64     int64 (arithmetic is exact modulo 2^64; the result is
  *                        the exact integer product when that fits int64)
+ *             PM_MODQ64  uint64 residue in [0, q), q = 2^64 - 59 (a prime)
+ *             or 24 bytes per term:
+ *             PM_Z192    exact integers: three uint64 words per term, the
+ *                        two's-complement form of a value in [-2^191, 2^191),
+ *                        least significant word first (coefs[3i..3i+2]).
+ *                        pm_mul forms the product modulo 2^64, 2^61 - 1 and
+ *                        2^64 - 59 and recovers each coefficient by the
+ *                        Chinese remainder theorem; it returns PM_EOVERFLOW
+ *                        unless bits(max|a_i|) + bits(max|b_j|) +
+ *                        bits(min(n_f, n_g)) <= 187, which keeps every output
+ *                        coefficient below 2^187 in magnitude (bits(x): the
+ *                        bit length).  pm_mul and pm_mul_bound only: the batch,
+ *                        prepared-batch, server, autotuner and no-allocation
+ *                        entry points return PM_EINVAL for it.
  *   Zero input coefficients are allowed; they contribute nothing.
  * Output keys are strictly ascending; no output coefficient is zero (for
  * PM_F64: exactly +0.0 or -0.0 is dropped).
@@ -58,14 +72,14 @@ extern "C" {
 #define PM_OK 0
 #define PM_EINVAL (-1)     /* null pointer, bad layout, negative size, key bits outside the fields */
 #define PM_EUNSORTED (-2)  /* input keys not strictly ascending */
-#define PM_EOVERFLOW (-3)  /* max_f[v] + max_g[v] does not fit the field of variable v */
-#define PM_ERANGE (-4)     /* residue >= p (PM_MODP61) or non-finite coefficient (PM_F64) */
+#define PM_EOVERFLOW (-3)  /* max_f[v] + max_g[v] does not fit the field of variable v (PM_Z192: also the 2^187 bound) */
+#define PM_ERANGE (-4)     /* residue >= p (PM_MODP61), >= q (PM_MODQ64) or non-finite coefficient (PM_F64) */
 #define PM_ECAPACITY (-5)  /* output capacity below the bound (pm_server_submit only) */
 #define PM_ENOMEM (-6)     /* workspace too small, a sparse product of more than 2^32 - 1 term pairs, or a server arena that can never hold the request */
 #define PM_EDEVICE (-7)    /* HIP runtime error; pm_last_error() has the message */
 #define PM_EBUSY (-8)      /* server: request queue full, retry later */
 
-typedef enum { PM_MODP61 = 0, PM_F64 = 1, PM_I64 = 2 } pm_ring;
+typedef enum { PM_MODP61 = 0, PM_F64 = 1, PM_I64 = 2, PM_MODQ64 = 3, PM_Z192 = 4 } pm_ring;
 
 /* nvars >= 1, bits >= 1, nvars * bits <= 64; ring one of pm_ring. */
 typedef struct {

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpolymul.so")
-SOURCES = ["pm_kernels.hip", "pm_api.hip", "pm_plan.cpp", "pm_server.cpp"]
+SOURCES = ["pm_kernels.hip", "pm_api.hip", "pm_crt.hip", "pm_plan.cpp", "pm_server.cpp"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -108,7 +108,8 @@ int HostStage::device_tmp(size_t bytes, void **out) {
 static int check_layout(const pm_layout *L) {
     if (!L) return PM_EINVAL;
     if (L->nvars < 1 || L->bits < 1 || (uint64_t)L->nvars * L->bits > 64) return PM_EINVAL;
-    if (L->ring != PM_MODP61 && L->ring != PM_F64 && L->ring != PM_I64) return PM_EINVAL;
+    if (L->ring != PM_MODP61 && L->ring != PM_F64 && L->ring != PM_I64 && L->ring != PM_MODQ64 && L->ring != PM_Z192)
+        return PM_EINVAL;
     if (L->reserved != 0) return PM_EINVAL;
     return PM_OK;
 }
@@ -281,6 +282,8 @@ int pm_mul_bound(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, 
     int rc = check_args(layout, 1, f, g, nullptr);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
+    if (layout->ring == PM_Z192)
+        return z192_bound(g_stage, layout, f, g, max_terms, workspace_bytes, (hipStream_t)stream, g_tune);
     return bound_impl(g_stage, layout, 1, f, g, max_terms, workspace_bytes, (hipStream_t)stream, g_tune);
 }
 
@@ -290,6 +293,8 @@ int pm_mul(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const 
     if (rc) return rc;
     if (!h) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
+    if (layout->ring == PM_Z192)
+        return z192_mul(g_stage, layout, f, g, h, workspace, workspace_bytes, (hipStream_t)stream, g_tune);
     return mul_impl(g_stage, layout, 1, f, g, h, workspace, workspace_bytes, (hipStream_t)stream, g_tune, nullptr);
 }
 
@@ -297,6 +302,7 @@ int pm_mul_batch_bound(const pm_layout *layout, int64_t count, const pm_cpoly *f
                        int64_t *max_terms, int64_t *workspace_bytes, void *stream) {
     int rc = check_args(layout, count, f, g, nullptr);
     if (rc) return rc;
+    if (layout->ring == PM_Z192) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     return bound_impl(g_stage, layout, count, f, g, max_terms, workspace_bytes, (hipStream_t)stream, g_tune);
 }
@@ -306,10 +312,12 @@ int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, cons
     int rc = check_args(layout, count, f, g, h);
     if (rc) return rc;
     if (count > 0 && !h) return PM_EINVAL;
+    if (layout->ring == PM_Z192) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     return mul_impl(g_stage, layout, count, f, g, h, workspace, workspace_bytes, (hipStream_t)stream, g_tune,
                     nullptr);
 }
+
 
 }  // extern "C"
 
@@ -362,7 +370,7 @@ extern "C" int pm_mul_noalloc(const pm_layout *layout, const pm_cpoly *f, const 
                               void *stream) {
     int rc = check_args(layout, 1, f, g, h);
     if (rc) return rc;
-    if (!h) return PM_EINVAL;
+    if (!h || layout->ring == PM_Z192) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     void *ws = nullptr;
     rc = scratch_address(&ws);
@@ -400,7 +408,7 @@ int pm_batch_prepare(const pm_layout *layout, int64_t count, const pm_cpoly *f, 
     *out = nullptr;
     int rc = check_args(layout, count, f, g, h);
     if (rc) return rc;
-    if (count < 1 || !h) return PM_EINVAL;
+    if (count < 1 || !h || layout->ring == PM_Z192) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t st = (hipStream_t)stream;
     const size_t need0 = stats_region_bytes((int)count, (int)layout->nvars) + sizeof(DevSeg) * count;
@@ -475,7 +483,7 @@ int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, c
                 int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine, int32_t *digits) {
     int rc = check_args(layout, 1, f, g, h);
     if (rc) return rc;
-    if (!h) return PM_EINVAL;
+    if (!h || layout->ring == PM_Z192) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t st = (hipStream_t)stream;
     // which path does this product take?
@@ -555,7 +563,7 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
                        const uint64_t *stats, int64_t *max_terms, int64_t *workspace_bytes) {
     int rc = check_layout(layout);
     if (rc) return rc;
-    if (count < 0 || (count > 0 && (!na || !nb || !stats))) return PM_EINVAL;
+    if (count < 0 || (count > 0 && (!na || !nb || !stats)) || layout->ring == PM_Z192) return PM_EINVAL;
     std::vector<SegInput> in(count);
     for (int64_t q = 0; q < count; q++) {
         if (na[q] < 0 || nb[q] < 0) return PM_EINVAL;
@@ -651,7 +659,7 @@ const char *pm_strerror(int code) {
         case PM_OK: return "ok";
         case PM_EINVAL: return "invalid argument (null pointer, bad layout, negative size or key bits outside the fields)";
         case PM_EUNSORTED: return "operand keys are not strictly ascending";
-        case PM_EOVERFLOW: return "exponent sum does not fit its field";
+        case PM_EOVERFLOW: return "exponent sum does not fit its field (PM_Z192: or the coefficient bound exceeds 2^187)";
         case PM_ERANGE: return "coefficient out of range (residue >= 2^61-1 or non-finite double)";
         case PM_ECAPACITY: return "output capacity below the result bound";
         case PM_ENOMEM: return "workspace or arena too small";

@@ -36,5 +36,10 @@ int bound_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly 
 int mul_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
              const pm_poly *h, void *ws, int64_t ws_bytes, hipStream_t st, const Tuning &tune, Plan *plan_out);
 Tuning &default_tuning();
+// Exact integer coefficients (PM_Z192) through three modular products.
+int z192_bound(HostStage &hs, const pm_layout *L, const pm_cpoly *f, const pm_cpoly *g, int64_t *max_terms,
+               int64_t *ws_bytes, hipStream_t st, const Tuning &tune);
+int z192_mul(HostStage &hs, const pm_layout *L, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *ws,
+             int64_t ws_bytes, hipStream_t st, const Tuning &tune);
 
 }  // namespace pm

@@ -14,7 +14,7 @@ typedef int32_t i32;
 
 constexpr u64 P61 = (1ull << 61) - 1;
 
-enum Ring : int { RING_MODP = 0, RING_F64 = 1, RING_I64 = 2 };
+enum Ring : int { RING_MODP = 0, RING_F64 = 1, RING_I64 = 2, RING_MODQ = 3 };
 
 // How one product (a "segment" of a launch) is computed.
 enum SegMode : int {
@@ -270,10 +270,35 @@ __host__ __device__ inline u64 reduce61(u64 x) {
     return r >= P61 ? r - P61 : r;
 }
 
+// Arithmetic mod the prime q = 2^64 - 59, using 2^64 = 59 (mod q).
+constexpr u64 Q64 = 0xFFFFFFFFFFFFFFC5ull;
+constexpr u64 Q64_C = 59;
+
+__host__ __device__ inline u64 addmodq(u64 a, u64 b) {
+    u64 s = a + b;
+    if (s < a) s += Q64_C;  // wrapped past 2^64: s + 59 < q
+    return s >= Q64 ? s - Q64 : s;
+}
+
+// x = hi * 2^64 + lo  ->  hi * 59 + lo, folded until it fits, then one
+// conditional subtraction.
+__device__ inline u64 foldq(u64 hi, u64 lo) {
+    const u64 t_lo = hi * Q64_C, t_hi = __umul64hi(hi, Q64_C);  // t_hi < 59
+    u64 s = lo + t_lo;
+    const u64 k = t_hi + (s < lo ? 1u : 0u);                       // <= 59
+    const u64 s2 = s + k * Q64_C;
+    s = s2 < s ? s2 + Q64_C : s2;                                   // a second wrap leaves s2 < 59^2
+    return s >= Q64 ? s - Q64 : s;
+}
+
+__device__ inline u64 mulmodq(u64 a, u64 b) { return foldq(__umul64hi(a, b), a * b); }
+
 template <int RING>
 __device__ inline u64 ring_mul(u64 a, u64 b) {
     if constexpr (RING == RING_MODP) {
         return mulmod61(a, b);
+    } else if constexpr (RING == RING_MODQ) {
+        return mulmodq(a, b);
     } else if constexpr (RING == RING_I64) {
         return a * b;  // two's-complement product modulo 2^64
     } else {
@@ -285,6 +310,8 @@ template <int RING>
 __device__ inline u64 ring_add(u64 a, u64 b) {
     if constexpr (RING == RING_MODP) {
         return addmod61(a, b);
+    } else if constexpr (RING == RING_MODQ) {
+        return addmodq(a, b);
     } else if constexpr (RING == RING_I64) {
         return a + b;
     } else {
@@ -304,15 +331,17 @@ __device__ inline bool ring_is_zero(u64 a) {
 // Order-free exact accumulation into a 64-bit cell (LDS or global).
 //   mod p: the cell holds a value congruent to the sum; a wrap past 2^64 is
 //          compensated by adding 8, since 2^64 = 8 (mod 2^61-1).
+//   mod q: the same with 2^64 = 59 (mod 2^64-59).
 //   int64: plain wrapping addition.
 template <int RING>
 __device__ inline void ring_atomic_acc(u64 *cell, u64 c) {
-    if constexpr (RING == RING_MODP) {
+    if constexpr (RING == RING_MODP || RING == RING_MODQ) {
+        constexpr u64 WRAP = RING == RING_MODP ? 8 : Q64_C;
         u64 add = c;
         while (true) {
             u64 old = atomicAdd((unsigned long long *)cell, (unsigned long long)add);
             if (old + add >= old) break;
-            add = 8;
+            add = WRAP;
         }
     } else {
         atomicAdd((unsigned long long *)cell, (unsigned long long)c);
@@ -323,6 +352,8 @@ template <int RING>
 __device__ inline u64 ring_cell_final(u64 x) {
     if constexpr (RING == RING_MODP) {
         return reduce61(x);
+    } else if constexpr (RING == RING_MODQ) {
+        return x >= Q64 ? x - Q64 : x;
     } else {
         return x;
     }

@@ -80,6 +80,7 @@ __global__ __launch_bounds__(ST_T) void k_stats(const DevSeg *segs, int nvars, i
                     if (used < 64 && (kk[r] >> used) != 0) fl |= ST_BADBITS;
                     if (i > 0 && !(kk[r] > kp[r])) fl |= ST_UNSORTED;
                     if (ring == RING_MODP && cc[r] >= P61) fl |= ST_RANGE;
+                    if (ring == RING_MODQ && cc[r] >= Q64) fl |= ST_RANGE;
                     if (ring == RING_F64 && ((cc[r] >> 52) & 0x7ff) == 0x7ff) fl |= ST_RANGE;
                 }
 #pragma unroll
@@ -1807,10 +1808,12 @@ hipError_t launch_pipeline(const Plan &P, const Ctx &C, hipStream_t st, int cus)
     }
     if (P.ksize == 4) {
         if (P.ring == RING_MODP) launch_typed<u32, RING_MODP>(P, C, st, cus);
+        else if (P.ring == RING_MODQ) launch_typed<u32, RING_MODQ>(P, C, st, cus);
         else if (P.ring == RING_I64) launch_typed<u32, RING_I64>(P, C, st, cus);
         else launch_typed<u32, RING_F64>(P, C, st, cus);
     } else {
         if (P.ring == RING_MODP) launch_typed<u64, RING_MODP>(P, C, st, cus);
+        else if (P.ring == RING_MODQ) launch_typed<u64, RING_MODQ>(P, C, st, cus);
         else if (P.ring == RING_I64) launch_typed<u64, RING_I64>(P, C, st, cus);
         else launch_typed<u64, RING_F64>(P, C, st, cus);
     }

@@ -314,6 +314,7 @@ int pm_server_submit(pm_server *s, const pm_layout *layout, const pm_cpoly *f, c
     if (!s || !ticket || !h) return PM_EINVAL;
     int rc = check_args(layout, 1, f, g, h);
     if (rc) return rc;
+    if (layout->ring == PM_Z192) return PM_EINVAL;
     // the capacity check against the bound needs the device statistics: the
     // scheduler fails a request whose result arrays are too small
     Request *r = new Request();

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "polymul.h")
 
 PM_OK, PM_EINVAL, PM_EUNSORTED, PM_EOVERFLOW, PM_ERANGE, PM_ECAPACITY, PM_ENOMEM, PM_EDEVICE, PM_EBUSY = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
-RING_CODE = {"modp": 0, "f64": 1, "i64": 2}
+RING_CODE = {"modp": 0, "f64": 1, "i64": 2, "modq": 3, "z192": 4}
 
 
 class pm_layout(ctypes.Structure):
@@ -137,7 +137,8 @@ def _stream_ptr(stream):
 # ----------------------------------------------------------------------------
 @dataclass
 class DevPoly:
-    """Term arrays on the GPU: keys int64 (u64 bits), coefs int64 / float64."""
+    """Term arrays on the GPU: keys int64 (u64 bits), coefs int64 / float64
+    (z192: an (n, 3) int64 array of two's-complement words)."""
     keys: object
     coefs: object
     n: int
@@ -145,7 +146,7 @@ class DevPoly:
     def numpy(self):
         k = self.keys[: self.n].cpu().numpy().view(np.uint64)
         c = self.coefs[: self.n].cpu().numpy()
-        if c.dtype == np.int64 and self.coef_kind == "modp":
+        if c.dtype == np.int64 and self.coef_kind in ("modp", "modq", "z192"):
             c = c.view(np.uint64)
         return k, c
 
@@ -193,7 +194,8 @@ def bound(layout, f: DevPoly, g: DevPoly, stream=None):
 def alloc_out(cap: int, ring: str):
     import torch
     k = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
-    c = torch.empty(max(cap, 1), dtype=torch.float64 if ring == "f64" else torch.int64, device="cuda")
+    shape = (max(cap, 1), 3) if ring == "z192" else (max(cap, 1),)
+    c = torch.empty(shape, dtype=torch.float64 if ring == "f64" else torch.int64, device="cuda")
     n = torch.zeros(1, dtype=torch.int64, device="cuda")
     return k, c, n
 
