@@ -22,24 +22,55 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sparse5_n12_modp_hbm_traffic.json")
 
 
-def measured_traffic(label):
-    """Scaled rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch of `label`,
-    or None when the kernels changed since the counters were taken."""
+KERNEL_SOURCES = ["pm_kernels.hip", "pm_bkt.hpp", "pm_ival.hpp", "pm_internal.hpp", "pm_plan.cpp", "pm_plan.hpp"]
+
+
+def kernel_source_hash():
+    """Hash of the sources that decide the product's kernels and launches."""
     import hashlib
+    d = os.path.join(ROOT, "paper_1303_7425_amd", "csrc")
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_profile():
     try:
         prof = json.load(open(TRAFFIC_PROFILE))
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_1303_7425_amd", "csrc", "pm_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if sha != prof.get("kernel_source_sha256_16"):
-        return None
-    e = prof["per_launch"].get(label)
+    return prof if prof.get("kernel_source_sha256_16") == kernel_source_hash() else None
+
+
+def measured_traffic(label):
+    """Scaled rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch of `label`,
+    or None when the kernels changed since the counters were taken."""
+    prof = _traffic_profile()
+    e = None if prof is None else prof["per_launch"].get(label)
     return None if e is None else e["fetch_bytes"] + e["write_bytes"]
+
+
+def measured_step_traffic():
+    """Scaled counter bytes (read + write) of all the path's kernels per
+    product, or None when the kernels changed since the counters were taken."""
+    prof = _traffic_profile()
+    if prof is None or not prof.get("steps"):
+        return None
+    return sum((e["fetch_bytes"] + e["write_bytes"]) * e["launches"] for e in prof["per_launch"].values()) / prof["steps"]
 
 
 # rocprofv3 kernel names -> the labels used in the summaries
 KERNEL_LABELS = [
+    ("k_bk_count", "bk_count (fine-bin counts)"),
+    ("k_bk_cut", "bk_cut (greedy cut into work items)"),
+    ("k_bk_scan", "bk_scan"),
+    ("k_bk_winfo", "bk_winfo"),
+    ("k_bk_scatter", "bk_scatter (pair indices to work items)"),
+    ("k_bk_reduce<", "bk_reduce (per-work-item LDS sum)"),
+    ("k_bk_oscan", "bk_oscan"),
+    ("k_bk_copy", "bk_copy (result placement)"),
     ("k_onesweep<unsigned int, unsigned int, 2, false, true>", "onesweep pass (pair indices)"),
     ("k_onesweep<unsigned int, unsigned int, 2, false, false>", "onesweep pass (pair indices, keys via cache)"),
     ("k_onesweep<unsigned int, unsigned int, 2, true, true>", "onesweep last pass (pair indices, writes keys)"),
@@ -70,7 +101,7 @@ def kernel_label(name):
     return None
 
 
-def traffic_summary(fetch_csv, write_csv):
+def traffic_summary(fetch_csv, write_csv, steps=None):
     """rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of a
     `bench.py --copy-calibration` run -> per-launch HBM bytes, each counter
     scaled by what it reads for the 512 MiB calibration copies; writes the
@@ -97,13 +128,20 @@ def traffic_summary(fetch_csv, write_csv):
             continue
         per[label] = {"fetch_bytes": sum(vs) / len(vs) * fetch_scale,
                       "write_bytes": sum(wr[name]) / len(wr[name]) * write_scale, "launches": len(vs)}
-    src = os.path.join(ROOT, "paper_1303_7425_amd", "csrc", "pm_kernels.hip")
-    out = {"kernel_source_sha256_16": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16],
+    # products in the profiled run: launches of a kernel that runs once per
+    # product (the statistics kernel also runs for the bound query)
+    once = ("bk_reduce (per-work-item LDS sum)", "zero_compact", "compact")
+    nsteps = steps or next((per[k]["launches"] for k in once if k in per), None)
+    out = {"kernel_source_sha256_16": kernel_source_hash(),
            "workload": "sparse 5-var n=12 mod p", "fetch_scale": fetch_scale, "write_scale": write_scale,
-           "per_launch": per}
+           "steps": nsteps, "per_launch": per}
     with open(TRAFFIC_PROFILE, "w") as fh:
         json.dump(out, fh, indent=1)
-    print(f"fetch scale {fetch_scale:.4f}, write scale {write_scale:.4f}, kernel source {out['kernel_source_sha256_16']}")
+    print(f"fetch scale {fetch_scale:.4f}, write scale {write_scale:.4f}, kernel source {out['kernel_source_sha256_16']}, "
+          f"{nsteps} products profiled")
+    if nsteps:
+        tot = sum((e["fetch_bytes"] + e["write_bytes"]) * e["launches"] for e in per.values()) / nsteps
+        print(f"all kernels, per product: {tot / 1e6:.1f} MB read + written")
     print("| kernel | launches | read MB (scaled) | write MB (scaled) |")
     print("|---|---|---|---|")
     for label, e in sorted(per.items(), key=lambda kv: -(kv[1]["fetch_bytes"] + kv[1]["write_bytes"])):
@@ -130,10 +168,11 @@ def parse():
     ap.add_argument("--ring", default="modp", choices=["modp", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", default="sparse", choices=["sparse", "batch", "serve"],
+    ap.add_argument("--workload", default="sparse", choices=["sparse", "batch", "serve", "drain"],
                     help="sparse: the large sparse product (default JSON line); batch: the 4096-product "
                          "batched workload, batched graph launches vs per-product calls; serve: Poisson "
-                         "arrivals through the continuous-batching server")
+                         "arrivals through the continuous-batching server; drain: batched products in "
+                         "waves with results copied to host memory while the next wave runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 512 MiB three times (counter scaling for HBM traffic)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -142,6 +181,9 @@ def parse():
                     help="summarize a rocprofv3 --stats kernel_stats.csv (no GPU needed)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--wave-gib", type=float, default=96.0, help="HBM per memory wave (outputs + workspace)")
+    ap.add_argument("--drain-products", type=int, default=512, help="first products of the batched workload")
+    ap.add_argument("--drain-device-gib", type=float, default=64.0)
+    ap.add_argument("--drain-host-gib", type=float, default=16.0)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.5, help="arrival rate as a fraction of saturation")
     return ap.parse_args()
@@ -221,6 +263,92 @@ def bench_batch(args):
     }
 
 
+def bench_drain(args):
+    """Batched products drained to pinned host memory wave by wave while the
+    next wave runs (pm_mul_batch_drain), against the same waves computed with
+    results left in HBM and against the D2H copy of the same bytes alone."""
+    import numpy as np
+    import torch
+
+    from paper_1303_7425_amd import polymul as pm
+    from paper_1303_7425_amd import workloads as W
+
+    ring = args.ring
+    sizes, rng = W.config4_sizes()
+    sizes = sizes[:args.drain_products]
+    log(f"[drain] generating {len(sizes)} pairs")
+    fs, gs = [], []
+    for na, nb in sizes.tolist():
+        fs.append(pm.to_device(W.random_sparse(rng, int(na), 6, 10, 15, ring)))
+        gs.append(pm.to_device(W.random_sparse(rng, int(nb), 6, 10, 15, ring)))
+    pairs = int((sizes[:, 0] * sizes[:, 1]).sum())
+    lay = (6, 10, ring)
+    terms = [0]
+    checksum = [0]
+
+    def on_result(k, keys, coefs):
+        terms[0] += keys.size
+        if keys.size:
+            checksum[0] ^= int(keys[-1])     # touch the drained data (last key of each result)
+
+    dev_bytes = int(args.drain_device_gib * (1 << 30))
+    host_bytes = int(args.drain_host_gib * (1 << 30))
+    pm.mul_batch_drain(lay, fs[:8], gs[:8], on_result, dev_bytes, host_bytes)   # warm-up
+    terms[0] = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    waves = pm.mul_batch_drain(lay, fs, gs, on_result, dev_bytes, host_bytes)
+    t_drain = time.perf_counter() - t0
+    drained_bytes = 16 * terms[0]
+    log(f"[drain] {waves} waves, {terms[0]} terms, {t_drain:.3f} s")
+    # the same products with results left in HBM (pm_mul_batch over chunks of
+    # about 32 GiB of outputs and workspace)
+    ws = pm.Workspace()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chunk, acc = [], 0.0
+    for q, (na, nb) in enumerate(sizes.tolist() + [(0, 0)]):
+        need = na * nb * 40.0
+        if chunk and (q == len(sizes) or acc + need > 32.0 * (1 << 30)):
+            call = pm.BatchCall(lay, [fs[i] for i in chunk], [gs[i] for i in chunk], ws)
+            call.run()
+            torch.cuda.synchronize()
+            del call
+            chunk, acc = [], 0.0
+        if q < len(sizes):
+            chunk.append(q)
+            acc += need
+    t_hbm = time.perf_counter() - t0
+    del ws
+    # the D2H copy of the same bytes alone, pinned, in 1 GiB pieces
+    piece = 1 << 30
+    src = torch.empty(piece, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(piece, dtype=torch.uint8, pin_memory=True)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    left = drained_bytes
+    while left > 0:
+        n = min(piece, left)
+        dst[:n].copy_(src[:n], non_blocking=True)
+        left -= n
+    torch.cuda.synchronize()
+    t_copy = time.perf_counter() - t0
+    del src, dst
+    return {
+        "metric": "term-products/s (batched, results drained to host)", "value": pairs / t_drain,
+        "unit": "term-products/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64" if ring == "modp" else "f64",
+        "data": "synthetic", "waves": waves, "drained_terms": terms[0], "drained_bytes": drained_bytes,
+        "drain_s": t_drain, "results_in_hbm_s": t_hbm, "copy_alone_s": t_copy,
+        "d2h_GBps_alone": drained_bytes / t_copy / 1e9,
+        "overlap": (t_hbm + t_copy - t_drain) / min(t_hbm, t_copy),
+        "config": {"workload": f"first {len(sizes)} products of the batched workload recipe (6 vars, 10 bits, "
+                               "exponents 0..15, log-uniform term counts in [50, 20000], seed 4)",
+                   "term_products": pairs, "device_buffer_GiB": args.drain_device_gib,
+                   "host_buffer_GiB": args.drain_host_gib},
+    }
+
+
 def bench_serve(args):
     """Poisson arrivals through the server; p50/p99 latency, sustained rate."""
     import numpy as np
@@ -285,6 +413,59 @@ def bench_serve(args):
     }
 
 
+def host_cpu():
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(f, g, call):
+    """The oracle's multiply on one host thread, timed around the C call alone
+    (inputs converted and the output allocated beforehand), on whole products
+    of the same workload until about 10 s of CPU work (at most 8)."""
+    import ctypes
+
+    import numpy as np
+
+    import oracle
+    log("[bench] oracle (CPU baseline)")
+    lay = f.layout
+    fk, fc = np.ascontiguousarray(f.keys, np.uint64), np.ascontiguousarray(f.coefs, oracle.COEF_DTYPE[lay.ring])
+    gk, gc = np.ascontiguousarray(g.keys, np.uint64), np.ascontiguousarray(g.coefs, oracle.COEF_DTYPE[lay.ring])
+    L = oracle.lib()
+    b = ctypes.c_int64(0)
+    assert L.oracle_bound(lay.nvars, lay.bits, fk.size, fk.ctypes.data, gk.size, gk.ctypes.data, ctypes.byref(b)) == 0
+    cap = int(b.value)
+    hk = np.zeros(cap, np.uint64)
+    hc = np.zeros(cap, oracle.COEF_DTYPE[lay.ring])
+    ha = np.zeros(cap, np.float64) if lay.ring == "f64" else None
+    nh = ctypes.c_int64(0)
+    reps, dt = 0, 0.0
+    while reps < 8 and (reps == 0 or dt < 10.0):
+        t = time.perf_counter()
+        rc = L.oracle_mul(lay.nvars, lay.bits, oracle.RING_CODE[lay.ring], fk.size, fk.ctypes.data, fc.ctypes.data,
+                          gk.size, gk.ctypes.data, gc.ctypes.data, cap, hk.ctypes.data, hc.ctypes.data,
+                          ha.ctypes.data if ha is not None else None, ctypes.byref(nh))
+        dt += time.perf_counter() - t
+        assert rc == 0
+        reps += 1
+    n = int(nh.value)
+    rk, rcf = call.result().numpy()
+    same = bool(np.array_equal(rk, hk[:n]) and np.array_equal(rcf.view(np.uint64), hc[:n].view(np.uint64)))
+    model, ncpu, naff = host_cpu()
+    products = len(f) * len(g)
+    return {"value": reps * products / dt, "unit": "term-products/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "nproc": naff, "cpu_count": ncpu,
+            "sample": f"{reps} full products of the same workload, oracle_mul alone on one thread, {dt:.2f} s; "
+                      f"GPU result {'identical' if same else 'DIFFERENT'}"}
+
+
 def main():
     args = parse()
     if args.traffic_summary:
@@ -309,6 +490,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "drain":
+        print(json.dumps(bench_drain(args)), flush=True)
         return
     f, g = W.config3(args.ring)
     layout = (5, 12, args.ring)
@@ -348,14 +532,30 @@ def main():
     staged, passes, kbytes, vbytes = info["staged"], info["passes"], info["key_bytes"], info["payload_bytes"]
     assert pm.last_call_status() == 0
     per_step = {k: round(v[0] / args.steps, 5) for k, v in prof.items()}
-    # dominant kernel: a radix pass that moves items only.  Pair-index sorts
-    # (4-byte payload) read and write the index alone (keys regenerated from
-    # cache-resident operand keys); combined sorts move key + coefficient.
-    sweep_ms, sweep_n = prof.get("onesweep", (0.0, 0))
-    sweep_avg_ms = sweep_ms / max(sweep_n, 1)
-    item_bytes = vbytes if vbytes == 4 else kbytes + vbytes
-    sweep_bytes = staged * item_bytes * 2  # read + write
-    achieved = sweep_bytes / (sweep_avg_ms * 1e-3) / 1e9 if sweep_avg_ms > 0 else 0.0
+    # dominant kernel: the profiled scope with the most time per product
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    dom_ms, dom_n = prof[dom]
+    dom_avg_ms = dom_ms / max(dom_n, 1)
+    pair_item = 8  # staged (compressed key, pair index), two u32
+    if dom == "bk_reduce":
+        # reads every staged pair once, writes each result term's key (u32)
+        # and coefficient (u64); operand coefficients come from cache
+        dom_bytes = products * pair_item + n_out * 12 + (len(f) + len(g)) * 8
+        dom_kernel, dom_label = "k_bk_reduce (per-work-item LDS sum)", "bk_reduce (per-work-item LDS sum)"
+    elif dom == "bk_scatter":
+        dom_bytes = products * pair_item
+        dom_kernel, dom_label = "k_bk_scatter (pair indices to work items)", "bk_scatter (pair indices to work items)"
+    else:
+        # a radix pass that moves items only: pair-index sorts (4-byte payload)
+        # read and write the index alone, combined sorts key + coefficient
+        item_bytes = vbytes if vbytes == 4 else kbytes + vbytes
+        dom_bytes = staged * item_bytes * 2
+        dom_kernel, dom_label = f"{dom} (radix pass)", "onesweep pass (pair indices)"
+    achieved = dom_bytes / (dom_avg_ms * 1e-3) / 1e9 if dom_avg_ms > 0 else 0.0
+    # effective bandwidth: the product's algorithmic floor (22 B per term
+    # product: inputs, output, one spill of combined tiles) over the whole step
+    floor_bytes = 22.0 * products
+    effective = floor_bytes / (ms_step * 1e-3) / 1e9
 
     if args.copy_calibration:
         src = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
@@ -366,22 +566,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        log("[bench] oracle (CPU baseline)")
-        # whole products of the same workload, repeated until about 10 s of
-        # CPU work (at most 8), the GPU result compared with the first
-        reps, dt = 0, 0.0
-        while reps < 8 and (reps == 0 or dt < 10.0):
-            t = time.perf_counter()
-            wk, wc, _ = oracle.mul(f, g)
-            dt += time.perf_counter() - t
-            reps += 1
-            if reps == 1:
-                gk, gc = call.result().numpy()
-                same = bool(np.array_equal(gk, wk) and np.array_equal(gc.view(np.uint64), wc.view(np.uint64)))
-        cpu = {"value": reps * products / dt, "unit": "term-products/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full products of the same workload, single thread, {dt:.2f} s; GPU result "
-                         f"{'identical' if same else 'DIFFERENT'}"}
+        cpu = cpu_baseline(f, g, call)
 
     out = {
         "metric": "term-products/s",
@@ -402,10 +587,13 @@ def main():
             "terms_f": len(f), "terms_g": len(g), "term_products": products, "output_terms": n_out,
             "bits_per_var": 12,
         },
-        "roofline": {"bound": "hbm", "kernel": "onesweep (one LSD radix pass of pair indices)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("onesweep pass (pair indices)") if args.ring == "modp" else None,
-                     "algorithmic_bytes_per_launch": sweep_bytes, "avg_launch_ms": sweep_avg_ms,
+                     "traffic": measured_traffic(dom_label) if args.ring == "modp" else None,
+                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_avg_ms,
+                     "effective": {"floor_bytes": floor_bytes, "achieved": effective,
+                                   "frac": effective / HBM_PEAK_GBS},
+                     "path_counter_bytes_per_product": measured_step_traffic() if args.ring == "modp" else None,
                      "sorted_items": staged, "passes": passes, "key_bytes": kbytes,
                      "payload_bytes": vbytes},
         "kernel_ms_per_step": per_step,

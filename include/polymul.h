@@ -170,6 +170,31 @@ int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, cons
  * exponent ranges stay within what was validated (prepare again otherwise).
  * Returns NULL in *out on error.
  */
+/*
+ * Batched products with their results drained to host memory while later
+ * products run: the overlap of host-side result handling with the products
+ * still in progress (Sections 4 and 6.3).  Products are taken in index order
+ * in waves; a wave is the longest run of consecutive products whose planned
+ * workspace and bound-sized device results fit half of `device_buffer`
+ * (device memory, 256-byte aligned; the two halves alternate between waves)
+ * and whose bound-sized results (16 bytes per term) fit `host_buffer` (host
+ * memory of host_bytes; pinned memory from hipHostMalloc lets the copies run
+ * beside the kernels, pageable memory makes them synchronous).  Each wave
+ * runs as one batch (as pm_mul_batch) on `stream`; its results are copied to
+ * `host_buffer` on an internal stream while the next wave's kernels run, and
+ * then `fn(user, k, keys, coefs, n)` is called for each product k of the wave
+ * in index order, from the calling thread, with the k-th result's n terms
+ * (keys ascending, coefficients in the layout's ring).  The pointers are valid
+ * only during the call.  Returns when every callback has returned; *waves
+ * receives the number of waves.  PM_ENOMEM if one product alone does not fit;
+ * PM_EINVAL for PM_Z192 or null / non-positive buffers; validation errors as
+ * pm_mul_batch (nothing is called back then).
+ */
+typedef void (*pm_drain_fn)(void *user, int64_t index, const uint64_t *keys, const void *coefs, int64_t n);
+int pm_mul_batch_drain(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                       void *device_buffer, int64_t device_bytes, void *host_buffer, int64_t host_bytes,
+                       pm_drain_fn fn, void *user, void *stream, int64_t *waves);
+
 typedef struct pm_batch pm_batch;
 int pm_batch_prepare(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
                      void *workspace, int64_t workspace_bytes, void *stream, pm_batch **out);

@@ -136,19 +136,22 @@ int check_args(const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cp
     return PM_OK;
 }
 
-// Validation + statistics round trip and planning for `count` products.
-// `dev` is device memory of at least stats_region_bytes + sizeof(DevSeg)*count.
-int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
-                   void *dev, hipStream_t st, const Tuning &tune, Plan &P) {
+// Validation + statistics round trip for `count` products: fills `in` and
+// returns the statistics and flags (inside the pinned staging, valid until the
+// next use of `hs`).  `dev` is device memory of at least stats_region_bytes +
+// sizeof(DevSeg)*count.
+int stats_roundtrip(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                    void *dev, hipStream_t st, std::vector<SegInput> &in, const uint64_t **stats,
+                    const uint32_t **flags) {
     const int S = (int)count, nv = (int)L->nvars;
     const size_t sreg = stats_region_bytes(S, nv);
     const size_t segb = sizeof(DevSeg) * S;
-    const size_t sb = stats_bytes(S, nv), fb = (size_t)S * 2 * 4;
+    const size_t sb = stats_bytes(S, nv);
     const size_t up_off = 0, dn_off = (segb + 255) & ~(size_t)255;
     int rc = hs.reserve(dn_off + sreg);
     if (rc) return rc;
     DevSeg *hseg = (DevSeg *)((char *)hs.pin + up_off);
-    std::vector<SegInput> in(S);
+    in.resize(S);
     for (int q = 0; q < S; q++) {
         DevSeg d = DevSeg();
         d.fk = f[q].keys;
@@ -171,9 +174,20 @@ int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cp
         set_error("validation", e);
         return PM_EDEVICE;
     }
-    (void)fb;
-    return plan_build(nv, (int)L->bits, L->ring, in, (const uint64_t *)hstats,
-                      (const uint32_t *)(hstats + ((sb + 255) & ~(size_t)255)), tune, P, device_cus());
+    *stats = (const uint64_t *)hstats;
+    *flags = (const uint32_t *)(hstats + ((sb + 255) & ~(size_t)255));
+    return PM_OK;
+}
+
+// Validation + statistics round trip and planning for `count` products.
+int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                   void *dev, hipStream_t st, const Tuning &tune, Plan &P) {
+    std::vector<SegInput> in;
+    const uint64_t *stats = nullptr;
+    const uint32_t *flags = nullptr;
+    int rc = stats_roundtrip(hs, L, count, f, g, dev, st, in, &stats, &flags);
+    if (rc) return rc;
+    return plan_build((int)L->nvars, (int)L->bits, L->ring, in, stats, flags, tune, P, device_cus());
 }
 
 // Upload the descriptor block of plan P (output pointers filled) and enqueue
@@ -318,6 +332,160 @@ int pm_mul_batch(const pm_layout *layout, int64_t count, const pm_cpoly *f, cons
                     nullptr);
 }
 
+
+// Batched products in waves, each wave's results drained to host memory and
+// handed to the caller while the next wave runs on the device.
+int pm_mul_batch_drain(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                       void *device_buffer, int64_t device_bytes, void *host_buffer, int64_t host_bytes,
+                       pm_drain_fn fn, void *user, void *stream, int64_t *waves_out) {
+    int rc = check_args(layout, count, f, g, nullptr);
+    if (rc) return rc;
+    if (layout->ring == PM_Z192 || !fn || !device_buffer || !host_buffer || device_bytes <= 0 || host_bytes <= 0)
+        return PM_EINVAL;
+    if ((uintptr_t)device_buffer & 255) return PM_EINVAL;
+    if (waves_out) *waves_out = 0;
+    if (count == 0) return PM_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t st = (hipStream_t)stream;
+    const int nv = (int)layout->nvars;
+    const size_t need0 = stats_region_bytes((int)count, nv) + sizeof(DevSeg) * count;
+    if ((size_t)device_bytes < need0) return PM_ENOMEM;
+    // one statistics round trip for all products: bounds and planning inputs
+    std::vector<SegInput> in;
+    const uint64_t *st_p = nullptr;
+    const uint32_t *fl_p = nullptr;
+    rc = stats_roundtrip(g_stage, layout, count, f, g, device_buffer, st, in, &st_p, &fl_p);
+    if (rc) return rc;
+    const size_t sw = (size_t)4 * nv;
+    std::vector<uint64_t> stats(st_p, st_p + (size_t)count * sw);
+    std::vector<uint32_t> flags(fl_p, fl_p + (size_t)count * 2);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t half = ((size_t)device_bytes / 2) & ~(size_t)255;
+    // products [a, e) as one wave: their planned workspace, bound-sized device
+    // outputs and counts must fit half of the device buffer, their bound-sized
+    // results the host buffer
+    std::vector<int64_t> bound(count);
+    auto wave_fits = [&](int64_t a, int64_t e, size_t *ws_out) -> int {
+        std::vector<SegInput> sub(in.begin() + a, in.begin() + e);
+        Plan P;
+        const int r = plan_build(nv, (int)layout->bits, layout->ring, sub, stats.data() + (size_t)a * sw,
+                                 flags.data() + (size_t)a * 2, g_tune, P, device_cus());
+        if (r) return r;
+        size_t dev = al(8 * (size_t)(e - a)), host = 0;
+        for (int64_t q = a; q < e; q++) {
+            bound[q] = P.bound[q - a];
+            dev += 2 * al(8 * (size_t)std::max<int64_t>(bound[q], 1));
+            host += 16 * (size_t)bound[q];
+        }
+        if (ws_out) *ws_out = P.total;
+        return (dev + P.total <= half && host <= (size_t)host_bytes) ? PM_OK : PM_ENOMEM;
+    };
+    std::vector<int64_t> starts;
+    for (int64_t a = 0; a < count;) {
+        int r = wave_fits(a, a + 1, nullptr);
+        if (r) return r;  // a single product that does not fit (or a validation error)
+        int64_t good = a + 1, step = 1;
+        while (good < count) {  // doubling, then bisection
+            const int64_t e = std::min<int64_t>(count, good + step);
+            if (wave_fits(a, e, nullptr) != PM_OK) break;
+            good = e;
+            step *= 2;
+        }
+        int64_t lo = good, hi = std::min<int64_t>(count, good + step);
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (wave_fits(a, mid, nullptr) == PM_OK) lo = mid;
+            else hi = mid;
+        }
+        starts.push_back(a);
+        a = lo;
+    }
+    starts.push_back(count);
+    const int64_t nw = (int64_t)starts.size() - 1;
+    hipStream_t cst = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cst, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        set_error("hipStreamCreate", e);
+        return PM_EDEVICE;
+    }
+    // device layout of a wave in its half: counts, then per product keys and
+    // coefficients (bound-sized), then the workspace
+    struct Wave {
+        int64_t a = 0, e = 0;
+        char *base = nullptr;
+        std::vector<size_t> ok, oc;
+        size_t ws_off = 0;
+    };
+    auto place = [&](int64_t w) {
+        Wave W;
+        W.a = starts[w];
+        W.e = starts[w + 1];
+        W.base = (char *)device_buffer + (size_t)(w & 1) * half;
+        size_t o = al(8 * (size_t)(W.e - W.a));
+        for (int64_t q = W.a; q < W.e; q++) {
+            W.ok.push_back(o);
+            o += al(8 * (size_t)std::max<int64_t>(bound[q], 1));
+            W.oc.push_back(o);
+            o += al(8 * (size_t)std::max<int64_t>(bound[q], 1));
+        }
+        W.ws_off = o;
+        return W;
+    };
+    std::vector<int64_t> counts;
+    // copy wave W's results to the host buffer on the copy stream (after its
+    // kernels, which the next wave's validation round trip has waited for),
+    // then hand them to the caller
+    auto drain = [&](const Wave &W) -> int {
+        const int64_t n = W.e - W.a;
+        counts.resize(n);
+        hipError_t x = hipMemcpyAsync(counts.data(), W.base, 8 * (size_t)n, hipMemcpyDeviceToHost, cst);
+        if (x == hipSuccess) x = hipStreamSynchronize(cst);
+        char *hp = (char *)host_buffer;
+        std::vector<std::pair<char *, char *>> at(n);
+        for (int64_t i = 0; i < n && x == hipSuccess; i++) {
+            const int64_t q = W.a + i, m = std::min(counts[i], bound[q]);
+            at[i] = {hp, hp + 8 * (size_t)m};
+            if (m > 0) {
+                x = hipMemcpyAsync(at[i].first, W.base + W.ok[i], 8 * (size_t)m, hipMemcpyDeviceToHost, cst);
+                if (x == hipSuccess)
+                    x = hipMemcpyAsync(at[i].second, W.base + W.oc[i], 8 * (size_t)m, hipMemcpyDeviceToHost, cst);
+            }
+            hp += 16 * (size_t)m;
+        }
+        if (x == hipSuccess) x = hipStreamSynchronize(cst);
+        if (x != hipSuccess) {
+            set_error("result drain", x);
+            return PM_EDEVICE;
+        }
+        for (int64_t i = 0; i < n; i++)
+            fn(user, W.a + i, (const uint64_t *)at[i].first, at[i].second, std::min(counts[i], bound[W.a + i]));
+        return PM_OK;
+    };
+    Wave prev;
+    bool have_prev = false;
+    for (int64_t w = 0; w < nw && rc == PM_OK; w++) {
+        Wave W = place(w);
+        const int64_t n = W.e - W.a;
+        std::vector<pm_poly> h(n);
+        for (int64_t i = 0; i < n; i++)
+            h[i] = pm_poly{std::max<int64_t>(bound[W.a + i], 0), (int64_t *)(W.base + 8 * i), (uint64_t *)(W.base + W.ok[i]),
+                           W.base + W.oc[i]};
+        rc = mul_impl(g_stage, layout, n, f + W.a, g + W.a, h.data(), W.base + W.ws_off,
+                      (int64_t)(half - W.ws_off), st, g_tune, nullptr);
+        if (rc == PM_OK && have_prev) rc = drain(prev);  // overlaps wave w on the device
+        prev = W;
+        have_prev = true;
+    }
+    if (rc == PM_OK && have_prev) {
+        e = hipStreamSynchronize(st);
+        rc = e == hipSuccess ? drain(prev) : PM_EDEVICE;
+        if (e != hipSuccess) set_error("drain", e);
+    }
+    (void)hipStreamSynchronize(cst);
+    (void)hipStreamDestroy(cst);
+    if (waves_out) *waves_out = nw;
+    return rc;
+}
 
 }  // extern "C"
 

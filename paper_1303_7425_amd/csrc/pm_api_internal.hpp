@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/polymul.h"
 #include "pm_plan.hpp"
 
@@ -27,6 +29,9 @@ struct HostStage {
 void set_error(const char *what, hipError_t e);
 int device_cus();
 int check_args(const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h);
+int stats_roundtrip(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
+                    void *dev, hipStream_t st, std::vector<SegInput> &in, const uint64_t **stats,
+                    const uint32_t **flags);
 int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
                    void *dev, hipStream_t st, const Tuning &tune, Plan &P);
 int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st);

@@ -90,6 +90,8 @@ def lib():
         L.pm_set_radix.argtypes = [ctypes.c_int32]
         L.pm_mul_noalloc.argtypes = [ctypes.POINTER(pm_layout), ctypes.POINTER(pm_cpoly), ctypes.POINTER(pm_cpoly),
                                      ctypes.POINTER(pm_poly), vp]
+        L.pm_mul_batch_drain.argtypes = [ctypes.POINTER(pm_layout), i64, ctypes.POINTER(pm_cpoly),
+                                         ctypes.POINTER(pm_cpoly), vp, i64, vp, i64, DRAIN_FN, vp, vp, i64p]
         L.pm_ival_grid.argtypes = [i64, i64, ctypes.c_int32, i64p, i64p]
         L.pm_ival_splitters.argtypes = [ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(ctypes.c_uint64), i64,
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), i64p]
@@ -340,6 +342,44 @@ class BatchCall:
             o = int(self.offsets[q])
             out.append((k[o:o + ns[q]], c[o:o + ns[q]]))
         return out
+
+
+DRAIN_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p,
+                            ctypes.c_int64)
+
+
+def mul_batch_drain(layout, fs, gs, on_result, device_bytes: int, host_bytes: int, stream=None):
+    """Products in waves with results drained to pinned host memory while the
+    next wave runs; on_result(k, keys, coefs) gets numpy views (valid only
+    during the call) of product k's result.  Returns the number of waves."""
+    import torch
+    L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
+    ring = {v: k for k, v in RING_CODE.items()}[L.ring]
+    cdt = np.float64 if ring == "f64" else (np.int64 if ring == "i64" else np.uint64)
+    count = len(fs)
+    cf = (pm_cpoly * max(count, 1))(*[_cpoly(p) for p in fs])
+    cg = (pm_cpoly * max(count, 1))(*[_cpoly(p) for p in gs])
+    dev = torch.empty(int(device_bytes), dtype=torch.uint8, device="cuda")
+    host = torch.empty(int(host_bytes), dtype=torch.uint8, pin_memory=True)
+    errors = []
+
+    def cb(_user, k, keys, coefs, n):
+        try:
+            kk = np.ctypeslib.as_array(keys, shape=(n,)) if n else np.zeros(0, np.uint64)
+            cc = (np.ctypeslib.as_array(ctypes.cast(coefs, ctypes.POINTER(ctypes.c_uint64)), shape=(n,)).view(cdt)
+                  if n else np.zeros(0, cdt))
+            on_result(int(k), kk, cc)
+        except Exception as exc:  # raised after the call returns
+            errors.append(exc)
+
+    fn = DRAIN_FN(cb)
+    waves = ctypes.c_int64(0)
+    _check(lib().pm_mul_batch_drain(ctypes.byref(L), count, cf, cg, ctypes.c_void_p(dev.data_ptr()), dev.numel(),
+                                    ctypes.c_void_p(host.data_ptr()), host.numel(), fn, None, _stream_ptr(stream),
+                                    ctypes.byref(waves)), "pm_mul_batch_drain")
+    if errors:
+        raise errors[0]
+    return int(waves.value)
 
 
 def mul_batch(layout, fs, gs, workspace=None, stream=None):
