@@ -246,6 +246,17 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
                        const uint64_t *stats, int64_t *max_terms, int64_t *workspace_bytes);
 
 /*
+ * Measured ceiling of the degree-box path's inner loop, for roofline
+ * reporting: times (HIP events on `stream`, which it synchronises) a kernel
+ * that does, per term pair, the work of the dense tile step (operand keys and
+ * coefficients from LDS, one ring product, one LDS compare-and-swap into a
+ * 4096-slot table at about seven pairs per monomial, one LDS atomic
+ * accumulation) with no HBM traffic, on 8 workgroups per CU.  *pairs_per_second
+ * receives the rate.  ring: PM_MODP61, PM_I64 or PM_MODQ64 (else PM_EINVAL).
+ */
+int pm_dense_ceiling(int32_t ring, double *pairs_per_second, void *stream);
+
+/*
  * Host-only helpers of the output-key interval split (Section 5, Fig. 2;
  * Section 2's intervals), computing what the interval path's sampling and
  * splitting kernels compute on the device.  No GPU access.
@@ -281,7 +292,9 @@ int pm_ival_splitters(const uint64_t *fkeys, int64_t na, const uint64_t *gkeys, 
  *                bins cut into work items of at most 8192 pairs, pair indices
  *                scattered once to their work items, each work item summed
  *                in LDS; products with fewer than 2^32 cells and pairs).
- *                Automatic selection takes 3 where it applies.
+ *                Automatic selection takes 3 where it applies for the
+ *                exact rings (FP64 keeps the pair-index sort unless 3 is
+ *                requested).
  *   allow_dense  0: never use the degree-box path
  * Results do not depend on these settings (FP64 sums every monomial's
  * products in row-major order on every path).
@@ -333,8 +346,9 @@ int pm_profile_enable(int32_t enable);
 int pm_profile_read(int32_t i, char *name, int32_t name_cap, double *total_ms, int64_t *launches);
 
 /*
- * Autotuner.  Runs h = f * g once per candidate setting (sparse path: key
- * intervals, pair-index sort and LDS tile combine, the two radix-sorted ones
+ * Autotuner.  Runs h = f * g once per candidate setting (sparse path:
+ * output-key work items, key intervals, pair-index sort and LDS tile combine,
+ * the two radix-sorted ones
  * with both digit schedules of pm_set_radix; tile shape for the degree-box
  * path), times each with HIP events on `stream`, and remembers the fastest
  * for the product's size class (ring, path, floor(log2(term pairs))).  Later

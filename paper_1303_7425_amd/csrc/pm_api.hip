@@ -142,7 +142,7 @@ int check_args(const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cp
 // sizeof(DevSeg)*count.
 int stats_roundtrip(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
                     void *dev, hipStream_t st, std::vector<SegInput> &in, const uint64_t **stats,
-                    const uint32_t **flags) {
+                    const uint32_t **flags, bool sync) {
     const int S = (int)count, nv = (int)L->nvars;
     const size_t sreg = stats_region_bytes(S, nv);
     const size_t segb = sizeof(DevSeg) * S;
@@ -169,7 +169,7 @@ int stats_roundtrip(HostStage &hs, const pm_layout *L, int64_t count, const pm_c
                                           (u32 *)(dbase + ((sb + 255) & ~(size_t)255)), st);
     char *hstats = (char *)hs.pin + dn_off;
     if (e == hipSuccess) e = hipMemcpyAsync(hstats, dbase, sreg, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && sync) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         set_error("validation", e);
         return PM_EDEVICE;
@@ -192,7 +192,7 @@ int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cp
 
 // Upload the descriptor block of plan P (output pointers filled) and enqueue
 // the pipeline.
-int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st) {
+int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st, hipStream_t ust) {
     int rc = hs.reserve(P.r_desc.bytes);
     if (rc) return rc;
     char *pin = (char *)hs.pin;
@@ -209,8 +209,12 @@ int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st) {
     if (!P.bk_tile_pre.empty()) memcpy(pin + (P.o_bk_tile_pre - d0), P.bk_tile_pre.data(), 8 * P.bk_tile_pre.size());
     if (!P.bk_seg.empty()) memcpy(pin + (P.o_bk_seg - d0), P.bk_seg.data(), 4 * P.bk_seg.size());
     if (!P.bk_sb_pre.empty()) memcpy(pin + (P.o_bk_sb_pre - d0), P.bk_sb_pre.data(), 8 * P.bk_sb_pre.size());
-    hipError_t e = hipMemcpyAsync((char *)ws + d0, pin, P.r_desc.bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hs.fixed ? hipStreamSynchronize(st) : hipEventRecord(hs.ev, st);
+    // the copy runs on `ust` (default: the launch stream); the launch stream
+    // then waits for it, so the staging is free once `ust` has run the copy
+    if (!ust) ust = st;
+    hipError_t e = hipMemcpyAsync((char *)ws + d0, pin, P.r_desc.bytes, hipMemcpyHostToDevice, ust);
+    if (e == hipSuccess) e = hs.fixed ? hipStreamSynchronize(ust) : hipEventRecord(hs.ev, ust);
+    if (e == hipSuccess && !hs.fixed && ust != st) e = hipStreamWaitEvent(st, hs.ev, 0);
     if (e != hipSuccess) {
         set_error("descriptor upload", e);
         return PM_EDEVICE;
@@ -219,14 +223,14 @@ int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st) {
     return PM_OK;
 }
 
-int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st) {
+int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st, hipStream_t ust) {
     for (int q = 0; q < P.nseg; q++) {
         P.segs[q].hk = h[q].keys;
         P.segs[q].hc = (u64 *)h[q].coefs;
         P.segs[q].n_out = h[q].n_out;
         P.segs[q].cap = h[q].capacity;
     }
-    int rc = upload_descriptors(hs, P, ws, st);
+    int rc = upload_descriptors(hs, P, ws, st, ust);
     if (rc) return rc;
     hipError_t e;
     g_last_counters = (char *)ws + P.o_counters;
@@ -672,12 +676,14 @@ int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, c
     if (dense) {
         for (int t = 0; t < N_TILE_CFGS; t++) cands.push_back({t, 0, -1});
     } else if (layout->ring != PM_F64) {
+        cands.push_back({-1, 3, -1});
         cands.push_back({-1, 2, -1});
         cands.push_back({-1, 0, B});
         cands.push_back({-1, 0, G});
         cands.push_back({0, 1, B});
         cands.push_back({0, 1, G});
     } else {
+        cands.push_back({-1, 3, -1});
         cands.push_back({-1, 2, -1});
         cands.push_back({-1, 0, B});
         cands.push_back({-1, 0, G});
@@ -744,6 +750,30 @@ int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na
     if (max_terms)
         for (int64_t q = 0; q < count; q++) max_terms[q] = P.bound[q];
     if (workspace_bytes) *workspace_bytes = (int64_t)P.total;
+    return PM_OK;
+}
+
+int pm_dense_ceiling(int32_t ring, double *pairs_per_second, void *stream) {
+    if (!pairs_per_second || (ring != PM_MODP61 && ring != PM_I64 && ring != PM_MODQ64)) return PM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int grid = device_cus() * 8, tiles = 64;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_dense_ceiling(ring, grid, tiles, st);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < 3 && e == hipSuccess; r++) e = launch_dense_ceiling(ring, grid, tiles, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        set_error("dense ceiling", e);
+        return PM_EDEVICE;
+    }
+    *pairs_per_second = 3.0 * grid * tiles * 4096.0 / (ms * 1e-3);
     return PM_OK;
 }
 

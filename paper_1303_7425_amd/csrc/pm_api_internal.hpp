@@ -31,11 +31,12 @@ int device_cus();
 int check_args(const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h);
 int stats_roundtrip(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
                     void *dev, hipStream_t st, std::vector<SegInput> &in, const uint64_t **stats,
-                    const uint32_t **flags);
+                    const uint32_t **flags, bool sync = true);
 int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
                    void *dev, hipStream_t st, const Tuning &tune, Plan &P);
-int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st);
-int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st);
+// ust: stream of the descriptor copy (null: st); st waits for it.
+int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st, hipStream_t ust = nullptr);
+int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st, hipStream_t ust = nullptr);
 int bound_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
                int64_t *max_terms, int64_t *ws_bytes, hipStream_t st, const Tuning &tune);
 int mul_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,

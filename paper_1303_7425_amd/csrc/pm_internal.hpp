@@ -38,6 +38,7 @@ constexpr int BK_SB_LOG = 12;
 constexpr int BK_SB = 1 << BK_SB_LOG;  // fine bins per super-bin (the unit of the greedy cut)
 constexpr int BK_CAP = 8192;           // pairs of a work item sorted in one LDS pass
 constexpr int BK_BIN_PAIRS = 8;        // about this many term pairs per fine bin
+constexpr long long TILE_LAUNCH_PAIRS = 1ll << 27;  // term pairs per tile-kernel launch (about 1 ms dense)
 constexpr int BK_RANK_LOG = 18;        // exact rings: key span (log2) a work item sums by rank in LDS
 
 // One work item: fine bins [bin_lo, bin_hi) of product q (bins local to the

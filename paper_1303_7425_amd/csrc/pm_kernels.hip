@@ -131,6 +131,8 @@ __global__ void k_fill(u64 *p, i64 n, u64 v) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
 }
 
+__global__ void k_set32(u32 *p, u32 v) { *p = v; }
+
 // ---------------------------------------------------------------------------
 // k_compress: operand keys -> mixed-radix index.  Term t of the flattened list
 // [seg0.f, seg0.g, seg1.f, ...] located through cpre (exclusive prefix).
@@ -181,10 +183,12 @@ __device__ inline u32 hash_slot(K ck, int hb) {
 // and accumulated there exactly (mod p or modulo 2^64).  The table's non-zero
 // entries then go either to the product's staging array (sparse; the offset
 // comes from a look-back over the product's earlier tiles, so the staging is
-// dense) or into the degree-box array (dense).
+// dense) or into the degree-box array (dense).  One launch takes the tiles
+// [t_begin, t_end): a large product runs as several bounded launches, so work
+// on other streams is not kept off the device for the whole product.
 // ---------------------------------------------------------------------------
 template <typename K, int RING, int TM, int TN, int HB>
-__global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
+__global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C, i64 t_begin, i64 t_end) {
     constexpr int HS = 1 << HB;
     constexpr int SPT = HS / NTHREADS;
     const K EMPTY = (K)~(K)0;
@@ -199,12 +203,12 @@ __global__ __launch_bounds__(NTHREADS) void k_tile(Ctx C) {
 
     const i64 tb = C.tb_tile;
     while (true) {
-        if (threadIdx.x == 0) s_tile = (i64)atomicAdd(&C.counters[CNT_TILE], 1u) * tb;
+        if (threadIdx.x == 0) s_tile = t_begin + (i64)atomicAdd(&C.counters[CNT_TILE], 1u) * tb;
         __syncthreads();
         const i64 t0 = s_tile;
-        if (t0 >= C.ntiles) break;
+        if (t0 >= t_end) break;
         __syncthreads();
-        for (i64 t = t0; t < min(t0 + tb, C.ntiles); t++) {
+        for (i64 t = t0; t < min(t0 + tb, t_end); t++) {
         const i32 ts = seg_search(C.tile_pre, C.ntseg, t);
         const int q = C.tile_seg[ts];
         const DevSeg &s = C.segs[q];
@@ -1635,6 +1639,64 @@ static int device_cus_cached() {
 
 static inline int grid_for(int64_t work, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(work, cap)); }
 
+// ---------------------------------------------------------------------------
+// Ceiling of the degree-box path's inner loop (for roofline reporting): the
+// same per-pair work as k_tile's expand-and-combine step on a 64 x 64 tile
+// (operand keys and coefficients read from LDS, one ring product, the hash of
+// the key, one LDS compare-and-swap that finds the key's slot and one LDS
+// atomic accumulation), repeated over `tiles` tiles per workgroup, with no
+// HBM traffic and no table flush.  Keys i*8 + j give 567 distinct slots per
+// tile, about seven pairs per monomial.
+// ---------------------------------------------------------------------------
+__device__ u64 g_ceiling_sink[1 << 14];
+
+template <int RING>
+__global__ __launch_bounds__(NTHREADS) void k_dense_ceiling(int tiles) {
+    constexpr int TM = 64, TN = 64, HB = 12, HS = 1 << HB;
+    const u32 EMPTY = ~0u;
+    __shared__ u32 s_fk[TM], s_gk[TN];
+    __shared__ u64 s_fc[TM], s_gc[TN];
+    __shared__ u32 s_hk[HS + HS / 16];
+    __shared__ u64 s_hv[HS + HS / 16];
+    auto pad = [](int h) { return h + (h >> 4); };
+    for (int e = threadIdx.x; e < TM; e += NTHREADS) {
+        s_fk[e] = (u32)e * 8u;
+        s_fc[e] = ((u64)(e + 1) * 0x9E3779B97F4A7C15ull + blockIdx.x) >> 4;  // < 2^60 < p
+    }
+    for (int e = threadIdx.x; e < TN; e += NTHREADS) {
+        s_gk[e] = (u32)e;
+        s_gc[e] = ((u64)(e + 7) * 0xC2B2AE3D27D4EB4Full) >> 4;
+    }
+    for (int e = threadIdx.x; e < HS + HS / 16; e += NTHREADS) {
+        s_hk[e] = EMPTY;
+        s_hv[e] = 0;
+    }
+    __syncthreads();
+    for (int t = 0; t < tiles; t++) {
+        for (int e = threadIdx.x; e < TM * TN; e += NTHREADS) {
+            const int i = e / TN, j = e % TN;
+            const u64 c = ring_mul<RING>(s_fc[i], s_gc[j]);
+            const u32 key = s_fk[i] + s_gk[j];
+            u32 h = hash_slot<u32>(key, HB);
+            for (int probe = 0; probe < HS; probe++) {
+                const u32 old = lds_cas<u32>(&s_hk[pad(h)], EMPTY, key);
+                if (old == EMPTY || old == key) break;
+                h = (h + 1) & (HS - 1);
+            }
+            ring_atomic_acc<RING>(&s_hv[pad(h)], c);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g_ceiling_sink[blockIdx.x & ((1 << 14) - 1)] = s_hv[pad(hash_slot<u32>(0, HB))];
+}
+
+hipError_t launch_dense_ceiling(int ring, int grid, int tiles, hipStream_t st) {
+    if (ring == RING_MODP) hipLaunchKernelGGL(k_dense_ceiling<RING_MODP>, dim3(grid), dim3(NTHREADS), 0, st, tiles);
+    else if (ring == RING_MODQ) hipLaunchKernelGGL(k_dense_ceiling<RING_MODQ>, dim3(grid), dim3(NTHREADS), 0, st, tiles);
+    else hipLaunchKernelGGL(k_dense_ceiling<RING_I64>, dim3(grid), dim3(NTHREADS), 0, st, tiles);
+    return hipGetLastError();
+}
+
 hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int ring, u64 *out, u32 *flags,
                         hipStream_t st) {
     ProfScope ps("stats", st);
@@ -1645,10 +1707,19 @@ hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int r
 template <typename K, int RING>
 static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid) {
     ProfScope ps("tile_combine", st);
-    switch (P.tile_cfg) {
-        case 0: hipLaunchKernelGGL((k_tile<K, RING, 32, 64, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
-        case 1: hipLaunchKernelGGL((k_tile<K, RING, 64, 64, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
-        default: hipLaunchKernelGGL((k_tile<K, RING, 128, 128, 12>), dim3(grid), dim3(NTHREADS), 0, st, C); break;
+    // launches of about TILE_LAUNCH_PAIRS term pairs each (about a millisecond
+    // on the dense path); the tile ticket restarts at each launch
+    const i64 tile_pairs = (i64)TILE_CFGS[P.tile_cfg].tm * TILE_CFGS[P.tile_cfg].tn;
+    const i64 per = std::max<i64>(1, TILE_LAUNCH_PAIRS / tile_pairs);
+    for (i64 b = 0; b < P.ntiles; b += per) {
+        const i64 e = std::min<i64>(P.ntiles, b + per);
+        if (b > 0) hipLaunchKernelGGL(k_set32, dim3(1), dim3(1), 0, st, C.counters + CNT_TILE, 0u);
+        const int g = (int)std::min<i64>(grid, e - b);
+        switch (P.tile_cfg) {
+            case 0: hipLaunchKernelGGL((k_tile<K, RING, 32, 64, 12>), dim3(g), dim3(NTHREADS), 0, st, C, b, e); break;
+            case 1: hipLaunchKernelGGL((k_tile<K, RING, 64, 64, 12>), dim3(g), dim3(NTHREADS), 0, st, C, b, e); break;
+            default: hipLaunchKernelGGL((k_tile<K, RING, 128, 128, 12>), dim3(g), dim3(NTHREADS), 0, st, C, b, e); break;
+        }
     }
 }
 

@@ -217,7 +217,9 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     // output-key work items: products with 32-bit compressed keys and pair
     // indices whose single monomials can never hold more than BK_CAP pairs
     // (at most min(na, nb) pairs share a monomial)
-    if (P.ksize == 4 && (tune.combine == -1 || tune.combine == 3)) {
+    // (automatic for the exact rings; FP64 sorts each work item by row and key
+    // in LDS, slower than the pair-index sort, so only on request)
+    if (P.ksize == 4 && (tune.combine == 3 || (tune.combine == -1 && ring != RING_F64))) {
         for (int q = 0; q < S; q++) {
             DevSeg &d = P.segs[q];
             if (d.mode != SEG_RAW) continue;

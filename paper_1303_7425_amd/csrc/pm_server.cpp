@@ -2,14 +2,18 @@
 // pm_server_* in include/polymul.h.
 //
 // One scheduler thread per server.  Submitted requests wait in a FIFO queue.
-// Each scheduling round takes the oldest requests that share a layout, plans
-// them as one batch (one validation round trip), and admits the batch when
-// its workspace fits the free part of the server's HBM arena; otherwise it
-// halves the batch, and a single request that does not fit yet waits for
-// earlier batches to complete (one that can never fit fails with PM_ENOMEM).
-// Admitted batches are launched round-robin on the server's streams, so new
-// work starts while earlier batches still run.  Completion is detected with
-// events; the arena range is then returned and the tickets finish.
+// The scheduler takes the oldest requests that share a layout and starts
+// their validation (statistics kernel and read-back on the planning stream)
+// without waiting for it; the read-back is polled like the completions.  Once
+// it has arrived, the batch is planned on the host; the longest prefix whose
+// workspace fits the free part of the server's HBM arena is admitted (the
+// rest waits for a later round; a single request that can never fit fails
+// with PM_ENOMEM).  Descriptors are uploaded on the planning stream and the
+// batch is launched round-robin on the server's streams, which wait for the
+// upload, so new work starts while earlier batches still run.  Completion is
+// detected with events; the batch's device error flag (read back behind its
+// kernels) decides between PM_OK and PM_EDEVICE, the arena range is returned
+// and the tickets finish.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,6 +95,18 @@ struct InFlight {
     std::vector<Request *> reqs;
     hipEvent_t ev = nullptr;
     int64_t off = 0, bytes = 0;
+    int slot = 0;  // pinned word receiving the batch's device error flag
+};
+
+// A batch whose statistics read-back is in flight.
+struct Validation {
+    bool active = false;
+    std::vector<Request *> group;
+    int64_t off0 = -1, need0 = 0;
+    hipEvent_t ev = nullptr;
+    std::vector<SegInput> in;
+    const uint64_t *stats = nullptr;
+    const uint32_t *flags = nullptr;
 };
 
 }  // namespace pm
@@ -113,6 +129,9 @@ struct pm_server {
     bool stop = false;
     uint64_t next_ticket = 1;
     HostStage stage;  // used by the scheduler thread only
+    Validation val;
+    uint32_t *err_host = nullptr;  // pinned, one word per in-flight batch
+    std::vector<int> free_slots;
     size_t max_pending = 1 << 16;
     int max_batch = 64;
     int max_inflight = 8;
@@ -126,157 +145,231 @@ static void finish(pm_server *s, Request *r, int status, double t) {
     if (status == PM_OK) s->latencies.push_back(r->latency);
 }
 
+// Remove r from the pending queue (caller holds s->mu).
+static void unqueue(pm_server *s, Request *r) {
+    auto it = std::find(s->pending.begin(), s->pending.end(), r);
+    if (it != s->pending.end()) s->pending.erase(it);
+}
+
+// The validation of s->val has arrived: plan, admit a prefix that fits the
+// arena and launch it.  Returns after launching or deferring the batch.
+static void plan_and_launch(pm_server *s, std::vector<hipEvent_t> &free_events) {
+    Validation &v = s->val;
+    const pm_layout L = v.group[0]->L;
+    const int nv = (int)L.nvars;
+    const size_t sw = (size_t)4 * nv;
+    int k = (int)v.group.size();
+    // the statistics live in the pinned staging, which the upload reuses
+    std::vector<uint64_t> stats(v.stats, v.stats + (size_t)k * sw);
+    std::vector<uint32_t> flags(v.flags, v.flags + (size_t)k * 2);
+    std::vector<SegInput> in = v.in;
+    std::vector<Request *> group = v.group;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->arena.release(v.off0, v.need0);
+    }
+    v.active = false;
+    const int cus = device_cus();
+    const Tuning &tune = default_tuning();
+    auto plan_prefix = [&](int n, Plan &P) {
+        std::vector<SegInput> sub(in.begin(), in.begin() + n);
+        return plan_build(nv, (int)L.bits, L.ring, sub, stats.data(), flags.data(), tune, P, cus);
+    };
+    // requests that fail validation or have too small result arrays fail alone
+    {
+        std::vector<Request *> g2;
+        std::vector<SegInput> in2;
+        std::vector<uint64_t> st2;
+        std::vector<uint32_t> fl2;
+        for (int i = 0; i < k; i++) {
+            Plan P1;
+            std::vector<SegInput> one{in[i]};
+            int rc = plan_build(nv, (int)L.bits, L.ring, one, stats.data() + i * sw, flags.data() + 2 * i, tune, P1,
+                                cus);
+            if (rc == PM_OK && group[i]->h.capacity < P1.bound[0]) rc = PM_ECAPACITY;
+            if (rc == PM_OK && (int64_t)P1.total > s->arena.size) rc = PM_ENOMEM;
+            if (rc != PM_OK) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                unqueue(s, group[i]);
+                finish(s, group[i], rc, now_us());
+                s->cv_done.notify_all();
+                continue;
+            }
+            g2.push_back(group[i]);
+            in2.push_back(in[i]);
+            st2.insert(st2.end(), stats.begin() + i * sw, stats.begin() + (i + 1) * sw);
+            fl2.insert(fl2.end(), flags.begin() + 2 * i, flags.begin() + 2 * i + 2);
+        }
+        group.swap(g2);
+        in.swap(in2);
+        stats.swap(st2);
+        flags.swap(fl2);
+        k = (int)group.size();
+    }
+    // the longest admissible prefix (halving); the rest stays queued
+    while (k >= 1) {
+        Plan P;
+        int rc = plan_prefix(k, P);
+        if (rc != PM_OK) return;  // not reached: every request planned alone
+        int64_t off = -1;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            off = s->arena.alloc((int64_t)P.total);
+        }
+        if (off < 0) {
+            if (k == 1) return;  // wait for memory; it is validated again later
+            k /= 2;
+            continue;
+        }
+        std::vector<pm_poly> h(k);
+        for (int i = 0; i < k; i++) h[i] = group[i]->h;
+        void *ws = (char *)s->arena_ptr + off;
+        hipStream_t st = s->streams[s->next_stream];
+        s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+        const int slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        s->err_host[slot] = 0;
+        rc = upload_and_launch(s->stage, P, h.data(), ws, st, s->plan_stream);
+        if (rc == PM_OK &&
+            hipMemcpyAsync(&s->err_host[slot], (char *)ws + P.o_counters + sizeof(u32) * CNT_ERR_SPIN, sizeof(u32),
+                           hipMemcpyDeviceToHost, st) != hipSuccess)
+            rc = PM_EDEVICE;
+        hipEvent_t ev = nullptr;
+        if (!free_events.empty()) {
+            ev = free_events.back();
+            free_events.pop_back();
+        } else {
+            (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        }
+        if (rc == PM_OK && hipEventRecord(ev, st) != hipSuccess) rc = PM_EDEVICE;
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (int i = 0; i < k; i++) unqueue(s, group[i]);
+        if (rc != PM_OK) {
+            const double t = now_us();
+            for (int i = 0; i < k; i++) finish(s, group[i], rc, t);
+            s->arena.release(off, (int64_t)P.total);
+            free_events.push_back(ev);
+            s->free_slots.push_back(slot);
+            s->cv_done.notify_all();
+        } else {
+            InFlight b;
+            b.reqs.assign(group.begin(), group.begin() + k);
+            b.ev = ev;
+            b.off = off;
+            b.bytes = (int64_t)P.total;
+            b.slot = slot;
+            s->inflight.push_back(b);
+        }
+        return;
+    }
+}
+
 static void scheduler(pm_server *s) {
     (void)hipSetDevice(s->device);
     std::vector<hipEvent_t> free_events;
+    Validation &v = s->val;
+    (void)hipEventCreateWithFlags(&v.ev, hipEventDisableTiming);
     while (true) {
-        // 1. completions
+        bool progress = false;
+        // 1. completions: the batch's error flag arrived before its event
         {
             std::vector<InFlight> still;
             for (auto &b : s->inflight) {
                 if (hipEventQuery(b.ev) == hipSuccess) {
                     const double t = now_us();
+                    const int status = s->err_host[b.slot] ? PM_EDEVICE : PM_OK;
                     std::lock_guard<std::mutex> lk(s->mu);
-                    for (Request *r : b.reqs) finish(s, r, PM_OK, t);
+                    for (Request *r : b.reqs) finish(s, r, status, t);
                     s->arena.release(b.off, b.bytes);
                     free_events.push_back(b.ev);
+                    s->free_slots.push_back(b.slot);
                     s->cv_done.notify_all();
+                    progress = true;
                 } else {
                     still.push_back(b);
                 }
             }
             s->inflight.swap(still);
         }
-        // 2. take the oldest requests sharing the head's layout
-        std::vector<Request *> group;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            if (s->stop && s->pending.empty() && s->inflight.empty()) break;
-            if (s->pending.empty() || (int)s->inflight.size() >= s->max_inflight) {
-                if (s->inflight.empty()) {
-                    s->cv_submit.wait_for(lk, std::chrono::milliseconds(1));
-                } else {
-                    lk.unlock();
-                    std::this_thread::sleep_for(std::chrono::microseconds(20));
-                }
-                continue;
-            }
-            const pm_layout L0 = s->pending.front()->L;
-            for (Request *r : s->pending) {
-                if (r->L.nvars == L0.nvars && r->L.bits == L0.bits && r->L.ring == L0.ring) group.push_back(r);
-                if ((int)group.size() >= s->max_batch) break;
-            }
-        }
-        // 3. plan; halve the batch until its workspace fits the free arena
-        int k = (int)group.size();
-        bool launched = false;
-        while (k >= 1 && !launched) {
-            std::vector<pm_cpoly> f(k), g(k);
-            std::vector<pm_poly> h(k);
-            for (int i = 0; i < k; i++) {
-                f[i] = group[i]->f;
-                g[i] = group[i]->g;
-                h[i] = group[i]->h;
-            }
-            int64_t need0 = (int64_t)(stats_region_bytes(k, (int)group[0]->L.nvars) + sizeof(DevSeg) * k);
-            int64_t off0 = -1;
-            {
+        // 2. a validation whose read-back has arrived
+        if (v.active) {
+            const hipError_t q = hipEventQuery(v.ev);
+            if (q == hipSuccess) {
+                plan_and_launch(s, free_events);
+                progress = true;
+            } else if (q != hipErrorNotReady) {
                 std::lock_guard<std::mutex> lk(s->mu);
-                off0 = s->arena.alloc(need0);
-            }
-            if (off0 < 0) break;  // not even room to validate: wait for completions
-            Plan P;
-            void *dev0 = (char *)s->arena_ptr + off0;
-            int rc = stats_and_plan(s->stage, &group[0]->L, k, f.data(), g.data(), dev0, s->plan_stream,
-                                    default_tuning(), P);
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                s->arena.release(off0, need0);
-            }
-            if (rc != PM_OK) {
-                if (k == 1) {
-                    // this request is invalid (or can never be planned): fail it alone
-                    std::lock_guard<std::mutex> lk(s->mu);
-                    s->pending.erase(std::find(s->pending.begin(), s->pending.end(), group[0]));
-                    finish(s, group[0], rc, now_us());
-                    s->cv_done.notify_all();
-                    launched = true;
-                    break;
+                for (Request *r : v.group) {
+                    unqueue(s, r);
+                    finish(s, r, PM_EDEVICE, now_us());
                 }
-                k /= 2;  // isolate the failing request
-                continue;
-            }
-            // result arrays must hold each product's bound
-            bool short_cap = false;
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                for (int i = 0; i < k; i++) {
-                    if (group[i]->h.capacity < P.bound[i]) {
-                        s->pending.erase(std::find(s->pending.begin(), s->pending.end(), group[i]));
-                        finish(s, group[i], PM_ECAPACITY, now_us());
-                        short_cap = true;
-                    }
-                }
-                if (short_cap) s->cv_done.notify_all();
-            }
-            if (short_cap) {
-                launched = true;  // regroup in the next round
-                break;
-            }
-            int64_t off = -1;
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                if ((int64_t)P.total > s->arena.size) {
-                    if (k == 1) {
-                        s->pending.erase(std::find(s->pending.begin(), s->pending.end(), group[0]));
-                        finish(s, group[0], PM_ENOMEM, now_us());
-                        s->cv_done.notify_all();
-                        launched = true;
-                        break;
-                    }
-                } else {
-                    off = s->arena.alloc((int64_t)P.total);
-                }
-            }
-            if (off < 0) {
-                if (k == 1) break;  // wait for memory
-                k /= 2;
-                continue;
-            }
-            // the statistics went to a scratch range; the plan's own workspace is `off`
-            void *ws = (char *)s->arena_ptr + off;
-            hipStream_t st = s->streams[s->next_stream];
-            s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
-            rc = upload_and_launch(s->stage, P, h.data(), ws, st);
-            hipEvent_t ev = nullptr;
-            if (!free_events.empty()) {
-                ev = free_events.back();
-                free_events.pop_back();
-            } else {
-                (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            }
-            if (rc == PM_OK && hipEventRecord(ev, st) != hipSuccess) rc = PM_EDEVICE;
-            std::lock_guard<std::mutex> lk(s->mu);
-            for (int i = 0; i < k; i++) s->pending.erase(std::find(s->pending.begin(), s->pending.end(), group[i]));
-            if (rc != PM_OK) {
-                const double t = now_us();
-                for (int i = 0; i < k; i++) finish(s, group[i], rc, t);
-                s->arena.release(off, (int64_t)P.total);
-                free_events.push_back(ev);
+                s->arena.release(v.off0, v.need0);
+                v.active = false;
                 s->cv_done.notify_all();
-            } else {
-                InFlight b;
-                b.reqs.assign(group.begin(), group.begin() + k);
-                b.ev = ev;
-                b.off = off;
-                b.bytes = (int64_t)P.total;
-                s->inflight.push_back(b);
             }
-            launched = true;
         }
-        if (!launched) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        // 3. start the validation of the oldest requests sharing a layout
+        if (!v.active && (int)s->inflight.size() < s->max_inflight) {
+            std::vector<Request *> group;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                if (!s->pending.empty()) {
+                    const pm_layout L0 = s->pending.front()->L;
+                    for (Request *r : s->pending) {
+                        if (r->L.nvars == L0.nvars && r->L.bits == L0.bits && r->L.ring == L0.ring) group.push_back(r);
+                        if ((int)group.size() >= s->max_batch) break;
+                    }
+                }
+            }
+            if (!group.empty()) {
+                const int k = (int)group.size();
+                const int64_t need0 = (int64_t)(stats_region_bytes(k, (int)group[0]->L.nvars) + sizeof(DevSeg) * k);
+                int64_t off0 = -1;
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    off0 = s->arena.alloc(need0);
+                }
+                if (off0 >= 0) {
+                    std::vector<pm_cpoly> f(k), g(k);
+                    for (int i = 0; i < k; i++) {
+                        f[i] = group[i]->f;
+                        g[i] = group[i]->g;
+                    }
+                    int rc = stats_roundtrip(s->stage, &group[0]->L, k, f.data(), g.data(),
+                                             (char *)s->arena_ptr + off0, s->plan_stream, v.in, &v.stats, &v.flags,
+                                             false);
+                    if (rc == PM_OK && hipEventRecord(v.ev, s->plan_stream) != hipSuccess) rc = PM_EDEVICE;
+                    if (rc != PM_OK) {
+                        std::lock_guard<std::mutex> lk(s->mu);
+                        for (Request *r : group) {
+                            unqueue(s, r);
+                            finish(s, r, rc, now_us());
+                        }
+                        s->arena.release(off0, need0);
+                        s->cv_done.notify_all();
+                    } else {
+                        v.group = group;
+                        v.off0 = off0;
+                        v.need0 = need0;
+                        v.active = true;
+                    }
+                    progress = true;
+                }
+            }
+        }
+        if (!progress) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->stop && s->pending.empty() && s->inflight.empty() && !v.active) break;
+            if (s->inflight.empty() && !v.active) {
+                s->cv_submit.wait_for(lk, std::chrono::milliseconds(1));
+            } else {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+            }
+        }
     }
     for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(v.ev);
 }
 
 extern "C" {
@@ -292,6 +385,14 @@ pm_server *pm_server_create(int64_t hbm_budget_bytes, int32_t nstreams) {
         return nullptr;
     }
     s->arena.init(hbm_budget_bytes);
+    e = hipHostMalloc((void **)&s->err_host, sizeof(uint32_t) * s->max_inflight, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        set_error("server error flags", e);
+        (void)hipFree(s->arena_ptr);
+        delete s;
+        return nullptr;
+    }
+    for (int i = 0; i < s->max_inflight; i++) s->free_slots.push_back(i);
     for (int i = 0; i < nstreams && e == hipSuccess; i++) {
         hipStream_t st;
         e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -302,6 +403,7 @@ pm_server *pm_server_create(int64_t hbm_budget_bytes, int32_t nstreams) {
         set_error("server streams", e);
         for (auto st : s->streams) (void)hipStreamDestroy(st);
         (void)hipFree(s->arena_ptr);
+        (void)hipHostFree(s->err_host);
         delete s;
         return nullptr;
     }
@@ -390,6 +492,7 @@ void pm_server_destroy(pm_server *s) {
     }
     if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
     if (s->arena_ptr) (void)hipFree(s->arena_ptr);
+    if (s->err_host) (void)hipHostFree(s->err_host);
     for (auto &kv : s->reqs) delete kv.second;
     delete s;
 }

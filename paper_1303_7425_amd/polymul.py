@@ -92,6 +92,7 @@ def lib():
                                      ctypes.POINTER(pm_poly), vp]
         L.pm_mul_batch_drain.argtypes = [ctypes.POINTER(pm_layout), i64, ctypes.POINTER(pm_cpoly),
                                          ctypes.POINTER(pm_cpoly), vp, i64, vp, i64, DRAIN_FN, vp, vp, i64p]
+        L.pm_dense_ceiling.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]
         L.pm_ival_grid.argtypes = [i64, i64, ctypes.c_int32, i64p, i64p]
         L.pm_ival_splitters.argtypes = [ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(ctypes.c_uint64), i64,
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), i64p]
@@ -440,6 +441,13 @@ def plan_from_stats(layout, na, nb, stats):
     rc = lib().pm_plan_from_stats(ctypes.byref(L), count, na_a, nb_a,
                                   st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), mt, ctypes.byref(wb))
     return rc, [int(mt[i]) for i in range(count)], int(wb.value)
+
+
+def dense_ceiling(ring: str, stream=None) -> float:
+    """Term pairs/s of the dense path's inner loop with no HBM traffic."""
+    r = ctypes.c_double(0)
+    _check(lib().pm_dense_ceiling(RING_CODE[ring], ctypes.byref(r), _stream_ptr(stream)), "pm_dense_ceiling")
+    return float(r.value)
 
 
 def ival_grid(na: int, nb: int, l: int):
