@@ -168,11 +168,16 @@ def parse():
     ap.add_argument("--ring", default="modp", choices=["modp", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", default="sparse", choices=["sparse", "batch", "serve", "drain"],
+    ap.add_argument("--workload", default="sparse", choices=["sparse", "batch", "serve", "drain", "dense"],
                     help="sparse: the large sparse product (default JSON line); batch: the 4096-product "
                          "batched workload, batched graph launches vs per-product calls; serve: Poisson "
                          "arrivals through the continuous-batching server; drain: batched products in "
-                         "waves with results copied to host memory while the next wave runs")
+                         "waves with results copied to host memory while the next wave runs; dense: the "
+                         "degree-box products (dense n=10 int64, n=20 mod p, Example 1 n=40 mod p) against "
+                         "the measured ceiling of their inner loop")
+    ap.add_argument("--combine", type=int, default=-1,
+                    help="sparse path mode for the sparse workload (-1 automatic, 0 pair-index radix sort, "
+                         "1 LDS tile combine, 2 output-key intervals, 3 output-key work items)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 512 MiB three times (counter scaling for HBM traffic)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -181,6 +186,8 @@ def parse():
                     help="summarize a rocprofv3 --stats kernel_stats.csv (no GPU needed)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--wave-gib", type=float, default=96.0, help="HBM per memory wave (outputs + workspace)")
+    ap.add_argument("--batch-rings", default="both", choices=["both", "one"],
+                    help="batch workload: mod p and FP64, or --ring only")
     ap.add_argument("--drain-products", type=int, default=512, help="first products of the batched workload")
     ap.add_argument("--drain-device-gib", type=float, default=64.0)
     ap.add_argument("--drain-host-gib", type=float, default=16.0)
@@ -194,72 +201,103 @@ def log(*a):
 
 
 def bench_batch(args):
-    """Batched workload: products in memory waves; each wave one prepared batch
-    (one HIP graph replay) vs the same products as sequential pm_mul calls."""
+    """Batched workload, like for like: every product of every memory wave is
+    timed on its own (no extrapolation) in two pairings with the same
+    validation policy on both sides:
+      validated  one pm_mul_batch per wave        vs one pm_mul per product
+      prepared   one HIP-graph replay per wave    vs one prepared single-product
+                                                    graph replay per product
+    The autotuner runs first on one product of each size class.  Mod p and
+    FP64 (--batch-rings both)."""
+    import math
+
     import numpy as np
     import torch
 
     from paper_1303_7425_amd import polymul as pm
     from paper_1303_7425_amd import workloads as W
 
-    ring = args.ring
-    sizes, rng = W.config4_sizes(count=args.batch_count)
-    log(f"[batch] generating {len(sizes)} pairs")
-    pairs_dev = []
-    for na, nb in sizes.tolist():
-        f = W.random_sparse(rng, int(na), 6, 10, 15, ring)
-        g = W.random_sparse(rng, int(nb), 6, 10, 15, ring)
-        pairs_dev.append((pm.to_device(f), pm.to_device(g)))
-    total_pairs = int((sizes[:, 0] * sizes[:, 1]).sum())
-    # waves: bound-sized outputs (16 B/term) + sort workspace (about 16 B/pair)
-    budget = args.wave_gib * (1 << 30)
-    waves, cur, acc = [], [], 0.0
-    for q, (na, nb) in enumerate(sizes.tolist()):
-        need = na * nb * 40.0
-        if cur and acc + need > budget:
+    rings = ["modp", "f64"] if args.batch_rings == "both" else [args.ring]
+    out = {}
+    for ring in rings:
+        sizes, rng = W.config4_sizes(count=args.batch_count)
+        log(f"[batch] {ring}: generating {len(sizes)} pairs")
+        fs, gs = [], []
+        for na, nb in sizes.tolist():
+            fs.append(pm.to_device(W.random_sparse(rng, int(na), 6, 10, 15, ring)))
+            gs.append(pm.to_device(W.random_sparse(rng, int(nb), 6, 10, 15, ring)))
+        lay = (6, 10, ring)
+        total_pairs = int((sizes[:, 0] * sizes[:, 1]).sum())
+        ws = pm.Workspace()
+        # autotuner: the first product of each size class (floor(log2(pairs)))
+        pm.autotune_reset()
+        tuned = {}
+        for q, (na, nb) in enumerate(sizes.tolist()):
+            c = int(math.log2(na * nb))
+            if c not in tuned:
+                tuned[c] = pm.autotune(lay, fs[q], gs[q], ws)
+        log(f"[batch] {ring}: autotuned {len(tuned)} size classes")
+        # memory waves: bound-sized outputs (16 B/term) + workspace (about 24 B/pair)
+        budget = args.wave_gib * (1 << 30)
+        waves, cur, acc = [], [], 0.0
+        for q, (na, nb) in enumerate(sizes.tolist()):
+            need = na * nb * 40.0
+            if cur and acc + need > budget:
+                waves.append(cur)
+                cur, acc = [], 0.0
+            cur.append(q)
+            acc += need
+        if cur:
             waves.append(cur)
-            cur, acc = [], 0.0
-        cur.append(q)
-        acc += need
-    if cur:
-        waves.append(cur)
-    log(f"[batch] {total_pairs:.3e} term pairs in {len(waves)} waves")
-    ws = pm.Workspace()
-    t_graph = 0.0
-    t_single = 0.0
-    n_terms = 0
-    for w, idx in enumerate(waves):
-        call = pm.BatchCall((6, 10, ring), [pairs_dev[q][0] for q in idx], [pairs_dev[q][1] for q in idx], ws)
-        call.prepare_graph()
-        call.launch_graph()              # warm-up replay
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        call.launch_graph()
-        torch.cuda.synchronize()
-        t_graph += time.perf_counter() - t0
-        n_terms += int(call.out_n.sum().item())
-        assert pm.last_call_status() == 0
-        # the same products one pm_mul each, sharing one workspace
-        calls = [pm.MulCall((6, 10, ring), pairs_dev[q][0], pairs_dev[q][1], ws) for q in idx[:64]]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for c in calls:
-            c.run()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        # per-product time measured on the first 64 of the wave, scaled by their pair share
-        share = sum(sizes[q][0] * sizes[q][1] for q in idx[:64]) / max(1, sum(sizes[q][0] * sizes[q][1] for q in idx))
-        t_single += dt / max(share, 1e-12)
-        del call, calls
-        log(f"[batch] wave {w}: {len(idx)} products, graph {t_graph:.3f}s cumulative")
+        t = {"batch_validated": 0.0, "single_validated": 0.0, "batch_graph": 0.0, "single_graph": 0.0}
+        n_terms = 0
+
+        def timed(fn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        for w, idx in enumerate(waves):
+            call = pm.BatchCall(lay, [fs[q] for q in idx], [gs[q] for q in idx], ws)
+            call.run()
+            t["batch_validated"] += timed(call.run)
+            call.prepare_graph()
+            call.launch_graph()
+            t["batch_graph"] += timed(call.launch_graph)
+            n_terms += int(call.out_n.sum().item())
+            assert pm.last_call_status() == 0
+            del call
+            for q in idx:
+                c = pm.MulCall(lay, fs[q], gs[q], ws)
+                c.run()
+                t["single_validated"] += timed(c.run)
+                del c
+                b = pm.BatchCall(lay, [fs[q]], [gs[q]], ws)
+                b.prepare_graph()
+                b.launch_graph()
+                t["single_graph"] += timed(b.launch_graph)
+                del b
+            log(f"[batch] {ring} wave {w}: {len(idx)} products, {t}")
+        out[ring] = {
+            "term_products": total_pairs, "output_terms": n_terms, "waves": len(waves),
+            "validated": {"batched_s": t["batch_validated"], "per_product_s": t["single_validated"],
+                          "speedup": t["single_validated"] / t["batch_validated"]},
+            "prepared": {"batched_graph_s": t["batch_graph"], "per_product_graph_s": t["single_graph"],
+                         "speedup": t["single_graph"] / t["batch_graph"]},
+            "autotuned_classes": {str(k): list(v) for k, v in sorted(tuned.items())},
+        }
+        del fs, gs, ws
+        torch.cuda.empty_cache()
+    main = out[rings[0]]
     return {
-        "metric": "term-products/s (batched)", "value": total_pairs / t_graph, "unit": "term-products/s",
-        "n_gpus": 1, "ms_per_step": t_graph * 1e3, "higher_is_better": True, "dtype": "u64" if ring == "modp" else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{len(sizes)} random sparse 6-var products, 10 bits/var, exponents 0..15, "
-                               "term counts log-uniform in [50, 20000], seed 4", "term_products": total_pairs,
-                   "output_terms": n_terms, "waves": len(waves)},
-        "batched_s": t_graph, "per_product_s_estimate": t_single, "speedup_batched_vs_per_product": t_single / t_graph,
+        "metric": "term-products/s (batched, prepared graph)", "value": main["term_products"] / main["prepared"]["batched_graph_s"],
+        "unit": "term-products/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "u64" if rings[0] == "modp" else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.batch_count} random sparse 6-var products, 10 bits/var, exponents 0..15, "
+                               "term counts log-uniform in [50, 20000], seed 4"},
+        "rings": out,
     }
 
 
@@ -349,8 +387,59 @@ def bench_drain(args):
     }
 
 
+def bench_dense(args):
+    """Degree-box products: time per whole product (validation included, count
+    read back) and term pairs/s against the measured ceiling of the dense
+    tile's inner loop (mulmod or int64 product + LDS compare-and-swap + LDS
+    atomic, no HBM traffic)."""
+    import numpy as np
+    import torch
+
+    from paper_1303_7425_amd import polymul as pm
+    from paper_1303_7425_amd import workloads as W
+
+    cases = [("dense 4-var n=10, int64 (config 1)", 10, "i64"), ("dense 4-var n=20, mod 2^61-1 (config 2)", 20, "modp"),
+             ("dense 4-var n=40, mod 2^61-1 (the paper's Example 1)", 40, "modp")]
+    ceil = {r: pm.dense_ceiling(r) for r in ("i64", "modp")}
+    rows = []
+    for name, n, ring in cases:
+        f = W.dense_power(n, 4, 16, ring)
+        g = W.add_constant(f, 1)
+        call = pm.MulCall((4, 16, ring), pm.to_device(f), pm.to_device(g))
+        steps = 3 if n == 40 else args.steps
+        for _ in range(2):
+            call.run()
+            call.n()
+        ts = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            call.run()
+            nout = call.n()
+            ts.append(time.perf_counter() - t0)
+        assert pm.last_call_status() == 0
+        ms = 1e3 * float(np.median(ts))
+        pairs = len(f) * len(g)
+        rate = pairs / (ms * 1e-3)
+        rows.append({"workload": name, "term_products": pairs, "output_terms": nout, "ms_per_product": ms,
+                     "term_products_per_s": rate, "ceiling_per_s": ceil[ring], "frac_of_ceiling": rate / ceil[ring]})
+        log(f"[dense] {name}: {ms:.3f} ms, {rate:.3e} pairs/s, {rate / ceil[ring]:.2f} of ceiling")
+        del call
+    return {"metric": "term-products/s (degree-box path) vs inner-loop ceiling", "value": rows[1]["term_products_per_s"],
+            "unit": "term-products/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "roofline": {"bound": "alu", "kernel": "k_tile (dense)", "achieved": rows[1]["term_products_per_s"],
+                         "peak": ceil["modp"], "unit": "term-products/s (measured inner-loop ceiling)",
+                         "frac": rows[1]["frac_of_ceiling"]},
+            "config": {"workload": "dense 4-var products f*(f+1), f = (1+x+y+z+t)^n, 16 bits/var"},
+            "ceiling_per_s": ceil, "cases": rows}
+
+
 def bench_serve(args):
-    """Poisson arrivals through the server; p50/p99 latency, sustained rate."""
+    """Poisson arrivals through the server.  Latency runs from each request's
+    scheduled arrival time to its completion (so a submit loop that falls
+    behind is charged, not hidden), with the submit lateness recorded; result
+    arrays come from pools per result-size class, so a busy slot of one class
+    does not hold back another."""
     import numpy as np
     import torch
 
@@ -358,56 +447,60 @@ def bench_serve(args):
     from paper_1303_7425_amd import workloads as W
 
     n_req = args.serve_requests
-    probe = W.config5_stream(200, rate_per_s=1e9, seed=5)
     reqs_all = W.config5_stream(n_req, rate_per_s=1.0, seed=5)   # arrival times rescaled below
     log(f"[serve] uploading {n_req} requests")
     dev = [(pm.to_device(r.f), pm.to_device(r.g)) for r in reqs_all]
     caps = [pm.bound((r.f.layout.nvars, r.f.layout.bits, "modp"), *d)[0] for r, d in zip(reqs_all, dev)]
-    pool_n = 48
-    maxcap = max(caps)
-    pool = [pm.alloc_out(maxcap, "modp") for _ in range(pool_n)]
+    per_class = 16
+    pools = {c: [pm.alloc_out(c, "modp") for _ in range(per_class)] for c in sorted(set(caps))}
     srv = pm.Server(64 << 30, nstreams=4)
 
     def run(rate):
-        owner = [None] * pool_n
-        tickets = []
-        t0 = time.perf_counter()
+        owner = {c: [None] * per_class for c in pools}
+        nxt = {c: 0 for c in pools}
+        tickets, t_sub = [], []
         arr = np.cumsum(np.random.Generator(np.random.PCG64(5)).exponential(1.0 / rate, size=n_req))
+        t0 = time.perf_counter()
         for i, r in enumerate(reqs_all):
-            slot = i % pool_n
-            if owner[slot] is not None:
-                srv.wait(owner[slot])
+            c = caps[i]
+            slot = nxt[c]
+            nxt[c] = (slot + 1) % per_class
+            if owner[c][slot] is not None:
+                srv.wait(owner[c][slot])
             while time.perf_counter() - t0 < arr[i]:
                 pass
-            owner[slot] = srv.submit((r.f.layout.nvars, r.f.layout.bits, "modp"), dev[i][0], dev[i][1], pool[slot])
-            tickets.append(owner[slot])
+            t_sub.append(time.perf_counter() - t0)
+            owner[c][slot] = srv.submit((r.f.layout.nvars, r.f.layout.bits, "modp"), dev[i][0], dev[i][1],
+                                        pools[c][slot])
+            tickets.append(owner[c][slot])
         for t in tickets:
             assert srv.wait(t) == 0
-        return time.perf_counter() - t0, tickets
+        elapsed = time.perf_counter() - t0
+        # latency from the scheduled arrival: submit lateness + server latency
+        late = np.array(t_sub) - arr
+        lat_ms = np.array([srv.latency_us(t) for t in tickets]) / 1e3 + late * 1e3
+        return elapsed, tickets, lat_ms, late
 
-    # saturation: all requests at once
-    lat0 = len(srv.latencies_us())
-    t_sat, _ = run(1e12)
     pairs = sum(len(r.f) * len(r.g) for r in reqs_all)
+    t_sat, _, _, _ = run(1e12)   # saturation: all requests at once
     sat_rate = n_req / t_sat
     log(f"[serve] saturated: {sat_rate:.1f} req/s, {pairs / t_sat:.3e} pairs/s")
-    lat1 = len(srv.latencies_us())
     rate = args.serve_load * sat_rate
-    t_run, tickets = run(rate)
-    lat = np.array(srv.latencies_us()[lat1:])
-    # the same latencies by request class (ticket i is request i)
-    per_class = {}
+    t_run, tickets, lat, late = run(rate)
+    by_class = {}
     for kind in sorted({r.kind for r in reqs_all}):
-        lk = np.array([srv.latency_us(t) for t, r in zip(tickets, reqs_all) if r.kind == kind])
-        per_class[kind] = {"requests": int(lk.size), "p50_ms": float(np.percentile(lk, 50)) / 1e3,
-                           "p99_ms": float(np.percentile(lk, 99)) / 1e3}
+        lk = np.array([x for x, r in zip(lat, reqs_all) if r.kind == kind])
+        by_class[kind] = {"requests": int(lk.size), "p50_ms": float(np.percentile(lk, 50)),
+                          "p99_ms": float(np.percentile(lk, 99))}
     srv.close()
     return {
-        "metric": "serve latency p50/p99", "value": float(np.percentile(lat, 50)) / 1e3, "unit": "ms (p50)",
-        "p99_ms": float(np.percentile(lat, 99)) / 1e3, "n_gpus": 1, "higher_is_better": False, "dtype": "u64",
-        "data": "synthetic", "arrival_rate_per_s": rate, "load_fraction_of_saturation": args.serve_load,
+        "metric": "serve latency p50/p99 (from scheduled arrival)", "value": float(np.percentile(lat, 50)),
+        "unit": "ms (p50)", "p99_ms": float(np.percentile(lat, 99)), "n_gpus": 1, "higher_is_better": False,
+        "dtype": "u64", "data": "synthetic", "arrival_rate_per_s": rate, "load_fraction_of_saturation": args.serve_load,
         "saturated_requests_per_s": sat_rate, "saturated_term_products_per_s": pairs / t_sat,
-        "sustained_term_products_per_s": pairs / t_run, "requests": n_req, "latency_by_class": per_class,
+        "sustained_term_products_per_s": pairs / t_run, "requests": n_req, "latency_by_class": by_class,
+        "submit_lateness_ms": {"p50": float(np.percentile(late, 50)) * 1e3, "p99": float(np.percentile(late, 99)) * 1e3,
+                               "max": float(late.max()) * 1e3},
         "config": {"workload": "Poisson arrivals (seed 5): 98% sparse 5-var pairs at power U{6..12} with fresh "
                                "residues, 2% dense (1+x+y+z+t)^30 x (same+1), mod 2^61-1"},
     }
@@ -494,6 +587,10 @@ def main():
     if args.workload == "drain":
         print(json.dumps(bench_drain(args)), flush=True)
         return
+    if args.workload == "dense":
+        print(json.dumps(bench_dense(args)), flush=True)
+        return
+    pm.set_tuning(-1, args.combine, True)
     f, g = W.config3(args.ring)
     layout = (5, 12, args.ring)
     fd, gd = pm.to_device(f), pm.to_device(g)
@@ -585,7 +682,8 @@ def main():
             "workload": "sparse 5-var product (1+x+y+2z^2+3t^3+5u^5)^12 * (1+u+t+2z^2+3y^3+5x^5)^12, "
                         + ("coefficients mod 2^61-1" if args.ring == "modp" else "FP64 coefficients U[-1,1] seed 3"),
             "terms_f": len(f), "terms_g": len(g), "term_products": products, "output_terms": n_out,
-            "bits_per_var": 12,
+            "bits_per_var": 12, "sparse_mode": {-1: "automatic", 0: "pair-index radix sort", 1: "LDS tile combine",
+                                                2: "output-key intervals", 3: "output-key work items"}[args.combine],
         },
         "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
