@@ -361,6 +361,17 @@ int pm_profile_read(int32_t i, char *name, int32_t name_cap, double *total_ms, i
  */
 int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
                 int64_t workspace_bytes, void *stream, int32_t *tile_cfg, int32_t *combine, int32_t *digits);
+/*
+ * Keep the autotuner's choices across processes (Section 5 tunes l once, at
+ * installation): pm_autotune_save writes every remembered choice to the text
+ * file `path` (one line per size class: ring, path, floor(log2(term pairs)),
+ * tile shape, sparse mode, digit schedule); pm_autotune_load adds the choices
+ * of such a file to the remembered ones (a class already remembered takes the
+ * file's choice).  Host only.  PM_EINVAL if the file cannot be written or
+ * read or a line is malformed (then nothing is loaded).
+ */
+int pm_autotune_save(const char *path);
+int pm_autotune_load(const char *path);
 /* Forget every autotuner choice. */
 void pm_autotune_reset(void);
 

@@ -733,6 +733,10 @@ int pm_autotune(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, c
 
 void pm_autotune_reset(void) { tune_reset(); }
 
+int pm_autotune_save(const char *path) { return path ? tune_save(path) : PM_EINVAL; }
+
+int pm_autotune_load(const char *path) { return path ? tune_load(path) : PM_EINVAL; }
+
 int pm_plan_from_stats(const pm_layout *layout, int64_t count, const int64_t *na, const int64_t *nb,
                        const uint64_t *stats, int64_t *max_terms, int64_t *workspace_bytes) {
     int rc = check_layout(layout);

@@ -1,10 +1,13 @@
 // Host planner: see pm_plan.hpp.
 #include "pm_plan.hpp"
 
+#include <stdio.h>
+
 #include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "../../include/polymul.h"
 
@@ -34,6 +37,41 @@ void tune_store(const TuneClass &c, int tile_cfg, int combine, int digits) {
 void tune_reset() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache.clear();
+}
+
+// Text file, one choice per line: ring dense log2pairs tile_cfg combine digits.
+int tune_save(const char *path) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = fopen(path, "w");
+    if (!f) return PM_EINVAL;
+    fprintf(f, "# polymul tuning: ring dense log2pairs tile_cfg combine digits\n");
+    for (auto &kv : g_tune_cache)
+        fprintf(f, "%d %d %d %d %d %d\n", kv.first.ring, kv.first.dense, kv.first.log2pairs, kv.second.tile_cfg,
+                kv.second.combine, kv.second.digits);
+    return fclose(f) == 0 ? PM_OK : PM_EINVAL;
+}
+
+int tune_load(const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f) return PM_EINVAL;
+    std::vector<std::pair<TuneClass, TuneChoice>> got;
+    char line[256];
+    int rc = PM_OK;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int r, d, l, t, c, g;
+        if (sscanf(line, "%d %d %d %d %d %d", &r, &d, &l, &t, &c, &g) != 6 || r < 0 || r > 4 || d < 0 || d > 1 ||
+            l < 0 || l > 127 || t < -1 || t >= N_TILE_CFGS || c < -1 || c > 3 || g < -1 || g > 1) {
+            rc = PM_EINVAL;
+            break;
+        }
+        got.push_back({TuneClass{r, d, l}, TuneChoice{t, c, g}});
+    }
+    fclose(f);
+    if (rc != PM_OK) return rc;  // nothing is taken from a malformed file
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &e : got) g_tune_cache[e.first] = e.second;
+    return PM_OK;
 }
 
 // Digit widths of the radix passes over the keys' significant bits: 8 bits

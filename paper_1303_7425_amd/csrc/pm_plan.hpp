@@ -46,6 +46,8 @@ struct TuneClass {
 bool tune_lookup(const TuneClass &c, int &tile_cfg, int &combine, int &digits);
 void tune_store(const TuneClass &c, int tile_cfg, int combine, int digits);
 void tune_reset();
+int tune_save(const char *path);
+int tune_load(const char *path);
 int log2_floor(uint64_t x);
 struct Plan;
 void set_digits(Plan &P, int schedule);

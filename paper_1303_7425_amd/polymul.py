@@ -93,6 +93,8 @@ def lib():
         L.pm_mul_batch_drain.argtypes = [ctypes.POINTER(pm_layout), i64, ctypes.POINTER(pm_cpoly),
                                          ctypes.POINTER(pm_cpoly), vp, i64, vp, i64, DRAIN_FN, vp, vp, i64p]
         L.pm_dense_ceiling.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]
+        L.pm_autotune_save.argtypes = [ctypes.c_char_p]
+        L.pm_autotune_load.argtypes = [ctypes.c_char_p]
         L.pm_ival_grid.argtypes = [i64, i64, ctypes.c_int32, i64p, i64p]
         L.pm_ival_splitters.argtypes = [ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(ctypes.c_uint64), i64,
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), i64p]
@@ -491,6 +493,16 @@ def set_radix(digits: int = -1):
 
 def autotune_reset():
     lib().pm_autotune_reset()
+
+
+def autotune_save(path: str):
+    """Write the autotuner's remembered choices to a text file."""
+    _check(lib().pm_autotune_save(str(path).encode()), "pm_autotune_save")
+
+
+def autotune_load(path: str):
+    """Add the choices of a file written by autotune_save."""
+    _check(lib().pm_autotune_load(str(path).encode()), "pm_autotune_load")
 
 
 class Server:

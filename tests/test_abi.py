@@ -121,3 +121,24 @@ def test_plan_sparse_exact_too_many_pairs():
         assert rc == pm.PM_ENOMEM, ring
     rc, _, _ = pm.plan_from_stats((2, 32, "modp"), [1 << 16], [(1 << 16) - 1], st[None, :])
     assert rc == pm.PM_OK                              # 2^31 pairs still fit
+
+
+def test_autotune_choices_save_and_load(tmp_path):
+    # the autotuner's per-size-class choices survive the process as a text file
+    src = tmp_path / "tune.txt"
+    src.write_text("# tuned once\n0 0 25 -1 3 -1\n1 0 26 -1 0 1\n0 1 20 2 0 -1\n")
+    pm.autotune_reset()
+    pm.autotune_load(src)
+    out = tmp_path / "out.txt"
+    pm.autotune_save(out)
+    lines = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
+    assert sorted(lines) == sorted(["0 0 25 -1 3 -1", "1 0 26 -1 0 1", "0 1 20 2 0 -1"])
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 0 25 -1 9 -1\n")            # sparse mode 9 does not exist
+    with pytest.raises(pm.PolymulError):
+        pm.autotune_load(bad)
+    pm.autotune_save(out)                         # nothing of the bad file was taken
+    assert sorted(ln for ln in out.read_text().splitlines() if not ln.startswith("#")) == sorted(lines)
+    pm.autotune_reset()
+    pm.autotune_save(out)
+    assert [ln for ln in out.read_text().splitlines() if not ln.startswith("#")] == []
