@@ -175,6 +175,9 @@ def parse():
                          "waves with results copied to host memory while the next wave runs; dense: the "
                          "degree-box products (dense n=10 int64, n=20 mod p, Example 1 n=40 mod p) against "
                          "the measured ceiling of their inner loop")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="tile shape of the LDS-combine and degree-box paths (-1 automatic, 0: 32x64, 1: 64x64, "
+                         "2: 128x128)")
     ap.add_argument("--combine", type=int, default=-1,
                     help="sparse path mode for the sparse workload (-1 automatic, 0 pair-index radix sort, "
                          "1 LDS tile combine, 2 output-key intervals, 3 output-key work items)")
@@ -399,8 +402,10 @@ def bench_dense(args):
     from paper_1303_7425_amd import workloads as W
 
     cases = [("dense 4-var n=10, int64 (config 1)", 10, "i64"), ("dense 4-var n=20, mod 2^61-1 (config 2)", 20, "modp"),
-             ("dense 4-var n=40, mod 2^61-1 (the paper's Example 1)", 40, "modp")]
+             ("dense 4-var n=40, mod 2^61-1 (the paper's Example 1)", 40, "modp"),
+             ("dense 4-var n=30, mod 2^61-1 (the serving mix's large request)", 30, "modp")]
     ceil = {r: pm.dense_ceiling(r) for r in ("i64", "modp")}
+    pm.set_tuning(args.tile, -1, True)
     rows = []
     for name, n, ring in cases:
         f = W.dense_power(n, 4, 16, ring)
@@ -430,7 +435,8 @@ def bench_dense(args):
             "roofline": {"bound": "alu", "kernel": "k_tile (dense)", "achieved": rows[1]["term_products_per_s"],
                          "peak": ceil["modp"], "unit": "term-products/s (measured inner-loop ceiling)",
                          "frac": rows[1]["frac_of_ceiling"]},
-            "config": {"workload": "dense 4-var products f*(f+1), f = (1+x+y+z+t)^n, 16 bits/var"},
+            "config": {"workload": "dense 4-var products f*(f+1), f = (1+x+y+z+t)^n, 16 bits/var",
+                       "tile": {-1: "automatic", 0: "32x64", 1: "64x64", 2: "128x128"}[args.tile]},
             "ceiling_per_s": ceil, "cases": rows}
 
 
