@@ -89,9 +89,9 @@ __device__ inline bool bk_slot(const BkTile &T, u32 p, u32 &r, u32 &c) {
 // Runs of equal values along the lanes: lanes whose value differs from the
 // lane below, and invalid lanes, start a run.  Returns the mask of run starts.
 __device__ inline u64 bk_run_starts(bool valid, u32 v) {
-    const u32 lane = lane_id();
-    const u32 prev = __shfl_up(v, 1, 64);
-    const bool head = valid && (lane == 0 || prev != v);
+    // the lower neighbour's value through a DPP wave shift (lane 0 keeps ~v)
+    const u32 prev = (u32)__builtin_amdgcn_update_dpp((int)~v, (int)v, 0x138, 0xF, 0xF, false);
+    const bool head = valid && prev != v;
     return __ballot(head) | ~__ballot(valid);
 }
 
