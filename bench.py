@@ -101,7 +101,7 @@ def kernel_label(name):
     return None
 
 
-def traffic_summary(fetch_csv, write_csv, steps=None):
+def traffic_summary(fetch_csv, write_csv, out_path=None, workload="sparse 5-var n=12 mod p", steps=None):
     """rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of a
     `bench.py --copy-calibration` run -> per-launch HBM bytes, each counter
     scaled by what it reads for the 512 MiB calibration copies; writes the
@@ -133,9 +133,9 @@ def traffic_summary(fetch_csv, write_csv, steps=None):
     once = ("bk_reduce (per-work-item LDS sum)", "zero_compact", "compact")
     nsteps = steps or next((per[k]["launches"] for k in once if k in per), None)
     out = {"kernel_source_sha256_16": kernel_source_hash(),
-           "workload": "sparse 5-var n=12 mod p", "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "workload": workload, "fetch_scale": fetch_scale, "write_scale": write_scale,
            "steps": nsteps, "per_launch": per}
-    with open(TRAFFIC_PROFILE, "w") as fh:
+    with open(out_path or TRAFFIC_PROFILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(f"fetch scale {fetch_scale:.4f}, write scale {write_scale:.4f}, kernel source {out['kernel_source_sha256_16']}, "
           f"{nsteps} products profiled")
@@ -183,8 +183,9 @@ def parse():
                          "1 LDS tile combine, 2 output-key intervals, 3 output-key work items)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 512 MiB three times (counter scaling for HBM traffic)")
-    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="summarize rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs (no GPU needed)")
+    ap.add_argument("--traffic-summary", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV [OUT_JSON]: summarize rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs "
+                         "(no GPU needed); OUT_JSON defaults to the default workload's traffic profile")
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV",
                     help="summarize a rocprofv3 --stats kernel_stats.csv (no GPU needed)")
     ap.add_argument("--batch-count", type=int, default=4096)
@@ -568,7 +569,9 @@ def cpu_baseline(f, g, call):
 def main():
     args = parse()
     if args.traffic_summary:
-        traffic_summary(*args.traffic_summary)
+        if len(args.traffic_summary) not in (2, 3):
+            sys.exit("--traffic-summary takes FETCH_CSV WRITE_CSV [OUT_JSON]")
+        traffic_summary(*args.traffic_summary[:3])
         return
     if args.trace_summary:
         trace_summary(args.trace_summary)

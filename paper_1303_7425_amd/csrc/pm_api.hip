@@ -223,7 +223,7 @@ int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st, hipStre
     return PM_OK;
 }
 
-int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st, hipStream_t ust) {
+int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st, hipStream_t ust, int part) {
     for (int q = 0; q < P.nseg; q++) {
         P.segs[q].hk = h[q].keys;
         P.segs[q].hc = (u64 *)h[q].coefs;
@@ -241,7 +241,7 @@ int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStr
     g_last.vsize = P.vsize;
     g_last.box = P.nbox;
     Ctx C = make_ctx(P, ws);
-    e = launch_pipeline(P, C, st, device_cus());
+    e = launch_pipeline(P, C, st, device_cus(), part);
     if (e != hipSuccess) {
         set_error("kernel launch", e);
         return PM_EDEVICE;

@@ -36,7 +36,9 @@ int stats_and_plan(HostStage &hs, const pm_layout *L, int64_t count, const pm_cp
                    void *dev, hipStream_t st, const Tuning &tune, Plan &P);
 // ust: stream of the descriptor copy (null: st); st waits for it.
 int upload_descriptors(HostStage &hs, Plan &P, void *ws, hipStream_t st, hipStream_t ust = nullptr);
-int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st, hipStream_t ust = nullptr);
+// part: PipelinePart of pm_launch.hpp (default: the whole pipeline).
+int upload_and_launch(HostStage &hs, Plan &P, const pm_poly *h, void *ws, hipStream_t st, hipStream_t ust = nullptr,
+                      int part = 0);
 int bound_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,
                int64_t *max_terms, int64_t *ws_bytes, hipStream_t st, const Tuning &tune);
 int mul_impl(HostStage &hs, const pm_layout *L, int64_t count, const pm_cpoly *f, const pm_cpoly *g,

@@ -1705,13 +1705,14 @@ hipError_t launch_stats(const DevSeg *segs, int nseg, int nvars, int bits, int r
 }
 
 template <typename K, int RING>
-static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid) {
+static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid, i64 only = -1) {
     ProfScope ps("tile_combine", st);
     // launches of about TILE_LAUNCH_PAIRS term pairs each (about a millisecond
-    // on the dense path); the tile ticket restarts at each launch
+    // on the dense path); the tile ticket restarts at each launch.  only >= 0:
+    // that launch alone.
     const i64 tile_pairs = (i64)TILE_CFGS[P.tile_cfg].tm * TILE_CFGS[P.tile_cfg].tn;
     const i64 per = std::max<i64>(1, TILE_LAUNCH_PAIRS / tile_pairs);
-    for (i64 b = 0; b < P.ntiles; b += per) {
+    for (i64 b = only >= 0 ? only * per : 0; b < P.ntiles; b += per) {
         const i64 e = std::min<i64>(P.ntiles, b + per);
         if (b > 0) hipLaunchKernelGGL(k_set32, dim3(1), dim3(1), 0, st, C.counters + CNT_TILE, 0u);
         const int g = (int)std::min<i64>(grid, e - b);
@@ -1720,7 +1721,15 @@ static void launch_tile(const Plan &P, const Ctx &C, hipStream_t st, int grid) {
             case 1: hipLaunchKernelGGL((k_tile<K, RING, 64, 64, 12>), dim3(g), dim3(NTHREADS), 0, st, C, b, e); break;
             default: hipLaunchKernelGGL((k_tile<K, RING, 128, 128, 12>), dim3(g), dim3(NTHREADS), 0, st, C, b, e); break;
         }
+        if (only >= 0) break;
     }
+}
+
+int64_t tile_launches(const Plan &P) {
+    if (P.ntiles <= 0) return 0;
+    const i64 tile_pairs = (i64)TILE_CFGS[P.tile_cfg].tm * TILE_CFGS[P.tile_cfg].tn;
+    const i64 per = std::max<i64>(1, TILE_LAUNCH_PAIRS / tile_pairs);
+    return (P.ntiles + per - 1) / per;
 }
 
 template <typename K, typename V, int RING>
@@ -1823,15 +1832,21 @@ static void launch_bkt(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
 }
 
 template <typename K, int RING>
-static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
-    if (P.nck > 0) {
+static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus, int part, i64 chunk) {
+    if (part == PART_CHUNK) {
+        if constexpr (RING != RING_F64) launch_tile<K, RING>(P, C, st, grid_for(P.ntiles, cus * 8), chunk);
+        return;
+    }
+    if (part != PART_TAIL && P.nck > 0) {
         ProfScope ps("compress", st);
         hipLaunchKernelGGL((k_compress<K>), dim3(grid_for((P.nck + NTHREADS - 1) / NTHREADS, cus * 16)), dim3(NTHREADS),
                            0, st, C, (const i64 *)((const char *)C.segs - P.o_segs + P.o_cpre), (i64)P.nck);
     }
-    if (P.ntiles > 0) {
-        if constexpr (RING != RING_F64) launch_tile<K, RING>(P, C, st, grid_for(P.ntiles, cus * 8));
+    if (P.ntiles > 0 && part != PART_TAIL) {
+        if constexpr (RING != RING_F64)
+            launch_tile<K, RING>(P, C, st, grid_for(P.ntiles, cus * 8), part == PART_HEAD ? 0 : -1);
     }
+    if (part == PART_HEAD) return;
     if (P.nival > 0) {
         if constexpr (sizeof(K) == 4) {
             {
@@ -1868,25 +1883,25 @@ static void launch_typed(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
     }
 }
 
-hipError_t launch_pipeline(const Plan &P, const Ctx &C, hipStream_t st, int cus) {
+hipError_t launch_pipeline(const Plan &P, const Ctx &C, hipStream_t st, int cus, int part, int64_t chunk) {
     // per-call zeroed state
     const size_t zbytes = P.r_zero.bytes;
     u64 *zp = (u64 *)((char *)C.segs - P.o_segs + P.r_zero.off);
-    {
+    if (part == PART_ALL || part == PART_HEAD) {
         ProfScope ps("fill", st);
         hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(zbytes / 8 + 255) / 256, cus * 8)), dim3(256), 0, st, zp,
                            (i64)(zbytes / 8), 0ull);
     }
     if (P.ksize == 4) {
-        if (P.ring == RING_MODP) launch_typed<u32, RING_MODP>(P, C, st, cus);
-        else if (P.ring == RING_MODQ) launch_typed<u32, RING_MODQ>(P, C, st, cus);
-        else if (P.ring == RING_I64) launch_typed<u32, RING_I64>(P, C, st, cus);
-        else launch_typed<u32, RING_F64>(P, C, st, cus);
+        if (P.ring == RING_MODP) launch_typed<u32, RING_MODP>(P, C, st, cus, part, chunk);
+        else if (P.ring == RING_MODQ) launch_typed<u32, RING_MODQ>(P, C, st, cus, part, chunk);
+        else if (P.ring == RING_I64) launch_typed<u32, RING_I64>(P, C, st, cus, part, chunk);
+        else launch_typed<u32, RING_F64>(P, C, st, cus, part, chunk);
     } else {
-        if (P.ring == RING_MODP) launch_typed<u64, RING_MODP>(P, C, st, cus);
-        else if (P.ring == RING_MODQ) launch_typed<u64, RING_MODQ>(P, C, st, cus);
-        else if (P.ring == RING_I64) launch_typed<u64, RING_I64>(P, C, st, cus);
-        else launch_typed<u64, RING_F64>(P, C, st, cus);
+        if (P.ring == RING_MODP) launch_typed<u64, RING_MODP>(P, C, st, cus, part, chunk);
+        else if (P.ring == RING_MODQ) launch_typed<u64, RING_MODQ>(P, C, st, cus, part, chunk);
+        else if (P.ring == RING_I64) launch_typed<u64, RING_I64>(P, C, st, cus, part, chunk);
+        else launch_typed<u64, RING_F64>(P, C, st, cus, part, chunk);
     }
     return hipGetLastError();
 }

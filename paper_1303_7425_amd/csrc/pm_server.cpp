@@ -13,7 +13,11 @@
 // upload, so new work starts while earlier batches still run.  Completion is
 // detected with events; the batch's device error flag (read back behind its
 // kernels) decides between PM_OK and PM_EDEVICE, the arena range is returned
-// and the tickets finish.
+// and the tickets finish.  A batch whose tile work spans several launches
+// (large dense products) is enqueued one tile launch at a time: after each,
+// the next waits while other batches are in flight or queued (at most
+// DENSE_YIELD_US), so small requests run beside one tile launch at most
+// instead of beside the whole product.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +32,7 @@
 
 #include "../../include/polymul.h"
 #include "pm_api_internal.hpp"
+#include "pm_launch.hpp"
 
 namespace pm {
 
@@ -91,11 +96,20 @@ struct Request {
     bool done = false;
 };
 
+constexpr double DENSE_YIELD_US = 2000.0;
+
 struct InFlight {
     std::vector<Request *> reqs;
     hipEvent_t ev = nullptr;
     int64_t off = 0, bytes = 0;
     int slot = 0;  // pinned word receiving the batch's device error flag
+    // staged tile launches: the plan, its stream, the next launch to enqueue
+    // (== nchunks: the tail), and when the previous part was seen done
+    bool staged = false;
+    Plan P;
+    hipStream_t st = nullptr;
+    int64_t next_chunk = 0, nchunks = 0;
+    double t_ready = -1;
 };
 
 // A batch whose statistics read-back is in flight.
@@ -229,8 +243,10 @@ static void plan_and_launch(pm_server *s, std::vector<hipEvent_t> &free_events) 
         const int slot = s->free_slots.back();
         s->free_slots.pop_back();
         s->err_host[slot] = 0;
-        rc = upload_and_launch(s->stage, P, h.data(), ws, st, s->plan_stream);
-        if (rc == PM_OK &&
+        const int64_t nchunks = tile_launches(P);
+        const bool staged = nchunks > 1;
+        rc = upload_and_launch(s->stage, P, h.data(), ws, st, s->plan_stream, staged ? PART_HEAD : PART_ALL);
+        if (rc == PM_OK && !staged &&
             hipMemcpyAsync(&s->err_host[slot], (char *)ws + P.o_counters + sizeof(u32) * CNT_ERR_SPIN, sizeof(u32),
                            hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = PM_EDEVICE;
@@ -258,6 +274,13 @@ static void plan_and_launch(pm_server *s, std::vector<hipEvent_t> &free_events) 
             b.off = off;
             b.bytes = (int64_t)P.total;
             b.slot = slot;
+            if (nchunks > 1) {
+                b.staged = true;
+                b.P = P;
+                b.st = st;
+                b.next_chunk = 1;
+                b.nchunks = nchunks;
+            }
             s->inflight.push_back(b);
         }
         return;
@@ -271,11 +294,50 @@ static void scheduler(pm_server *s) {
     (void)hipEventCreateWithFlags(&v.ev, hipEventDisableTiming);
     while (true) {
         bool progress = false;
-        // 1. completions: the batch's error flag arrived before its event
+        // 1. completions: the batch's error flag arrived before its event;
+        // a staged batch whose last part is done enqueues its next part, after
+        // yielding to other work for at most DENSE_YIELD_US
         {
+            bool others = false;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                others = !s->pending.empty() || v.active;
+            }
+            for (auto &b : s->inflight) others = others || !b.staged;
             std::vector<InFlight> still;
             for (auto &b : s->inflight) {
-                if (hipEventQuery(b.ev) == hipSuccess) {
+                if (b.staged && hipEventQuery(b.ev) == hipSuccess) {
+                    const double t = now_us();
+                    if (b.t_ready < 0) b.t_ready = t;
+                    if (others && t - b.t_ready < DENSE_YIELD_US) {
+                        still.push_back(b);
+                        continue;
+                    }
+                    void *ws = (char *)s->arena_ptr + b.off;
+                    const Ctx C = make_ctx(b.P, ws);
+                    hipError_t e = hipSuccess;
+                    if (b.next_chunk < b.nchunks) {
+                        e = launch_pipeline(b.P, C, b.st, device_cus(), PART_CHUNK, b.next_chunk);
+                        b.next_chunk++;
+                    } else {
+                        e = launch_pipeline(b.P, C, b.st, device_cus(), PART_TAIL);
+                        if (e == hipSuccess)
+                            e = hipMemcpyAsync(&s->err_host[b.slot], (char *)ws + b.P.o_counters + sizeof(u32) * CNT_ERR_SPIN,
+                                               sizeof(u32), hipMemcpyDeviceToHost, b.st);
+                        b.staged = false;
+                    }
+                    if (e == hipSuccess) e = hipEventRecord(b.ev, b.st);
+                    if (e != hipSuccess) {
+                        s->err_host[b.slot] = 1;  // reported as PM_EDEVICE once the stream drains
+                        b.staged = false;
+                        (void)hipEventRecord(b.ev, b.st);
+                    }
+                    b.t_ready = -1;
+                    progress = true;
+                    still.push_back(b);
+                    continue;
+                }
+                if (!b.staged && hipEventQuery(b.ev) == hipSuccess) {
                     const double t = now_us();
                     const int status = s->err_host[b.slot] ? PM_EDEVICE : PM_OK;
                     std::lock_guard<std::mutex> lk(s->mu);

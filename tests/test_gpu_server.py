@@ -106,3 +106,37 @@ def test_server_errors_and_budget():
     n = int(out[2].item())
     assert np.array_equal(out[0][:n].cpu().numpy().view(np.uint64), want[0])
     srv.close()
+
+
+def test_server_staged_dense_beside_small_requests():
+    """A dense product whose tile work spans several launches is enqueued one
+    launch at a time and yields to the small requests around it; its result
+    and theirs equal the single-call results."""
+    import torch
+    pm = _pm()
+    srv = pm.Server(8 << 30, nstreams=4)
+    dense = W.dense_power(22, 4, 16, "modp")           # 14950 terms: about 2.2e8 pairs, two or more tile launches
+    items = []
+
+    def submit(f, g):
+        lay = (f.layout.nvars, f.layout.bits, "modp")
+        fd, gd = pm.to_device(f), pm.to_device(g)
+        cap, _ = pm.bound(lay, fd, gd)
+        out = pm.alloc_out(cap, "modp")
+        items.append((lay, fd, gd, out, srv.submit(lay, fd, gd, out)))
+
+    submit(dense, W.add_constant(dense, 1))
+    rng = W.rng_for(77)
+    for k in range(12):
+        submit(W.with_random_coefs(W.sparse_power(4 + k % 4, "f"), rng, "modp"),
+               W.with_random_coefs(W.sparse_power(4 + (k * 3) % 4, "g"), rng, "modp"))
+    for *_, t in items:
+        assert srv.wait(t) == pm.PM_OK
+    torch.cuda.synchronize()
+    for lay, fd, gd, out, t in items:
+        n = int(out[2].item())
+        ak, ac = pm.mul(lay, fd, gd).numpy()
+        assert n == ak.size
+        assert np.array_equal(out[0][:n].cpu().numpy().view(np.uint64), ak)
+        assert np.array_equal(out[1][:n].cpu().numpy().view(np.uint64), ac)
+    srv.close()
