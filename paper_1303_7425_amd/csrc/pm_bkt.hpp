@@ -1258,25 +1258,35 @@ __global__ __launch_bounds__(BR_T) __attribute__((amdgpu_waves_per_eu(4))) void 
 
 // Result offsets: per product, the exclusive prefix of the work items'
 // result counts in ticket (key) order; the product's term count (one
-// workgroup).
+// workgroup, BO_IPT work items per thread per chunk, every load of a chunk
+// issued before the first use).
+constexpr int BO_IPT = 8;
 __global__ __launch_bounds__(BC_T) void k_bk_oscan(Ctx C) {
     __shared__ u64 s_v[BC_T / 64];
     __shared__ u32 s_f[BC_T / 64];
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
     const i64 ntk = (i64)C.bk_sbtb[C.bk_nsb];
-    u64 carry = 0;
-    for (i64 b = 0; b < ntk; b += BC_T) {
-        const i64 t = b + threadIdx.x;
-        u64 v = 0;
-        u32 f = 0, last = 0;
-        if (t < ntk) {
-            v = C.bk_u[t] & 0x7FFFFFFFu;
-            f = C.bk_wi[t].first;
-            last = C.bk_wi[t].last;
+    u64 carry = 0;  // running sum of the product in progress at the chunk's start
+    for (i64 b = 0; b < ntk; b += (i64)BC_T * BO_IPT) {
+        const i64 t0 = b + (i64)threadIdx.x * BO_IPT;
+        u32 v[BO_IPT];
+        u32 fl = 0, la = 0;  // bit e: work item t0 + e is its product's first / last
+#pragma unroll
+        for (int e = 0; e < BO_IPT; e++) {
+            const i64 t = t0 + e;
+            v[e] = 0;
+            if (t < ntk) {
+                v[e] = C.bk_u[t] & 0x7FFFFFFFu;
+                fl |= (C.bk_wi[t].first ? 1u : 0u) << e;
+                la |= (C.bk_wi[t].last ? 1u : 0u) << e;
+            }
         }
-        // inclusive segmented scan: a product's first work item restarts the sum
-        u32 fi = f;
-        u64 vi = v;
+        // the thread's (restarted, sum since its last restart)
+        u32 fi = fl ? 1u : 0u;
+        u64 vi = 0;
+#pragma unroll
+        for (int e = 0; e < BO_IPT; e++) vi = ((fl >> e) & 1u) ? (u64)v[e] : vi + v[e];
+        // inclusive segmented scan over the wave's threads
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const u32 fu = __shfl_up(fi, d, 64);
@@ -1290,13 +1300,26 @@ __global__ __launch_bounds__(BC_T) void k_bk_oscan(Ctx C) {
             s_v[w] = vi;
             s_f[w] = fi;
         }
+        // this thread's exclusive part within the wave
+        u32 fe = __shfl_up(fi, 1, 64);
+        u64 ve = ((u64)__shfl_up((u32)(vi >> 32), 1, 64) << 32) | __shfl_up((u32)vi, 1, 64);
+        if (lane == 0) {
+            fe = 0;
+            ve = 0;
+        }
         __syncthreads();
-        u64 cin = carry;  // carry into this wave: the chunk carry, then earlier waves
+        u64 cin = carry;  // the chunk carry, then the earlier waves, then the earlier lanes
         for (u32 ww = 0; ww < w; ww++) cin = s_f[ww] ? s_v[ww] : cin + s_v[ww];
-        const u64 incl = fi ? vi : cin + vi;
-        if (t < ntk) {
-            C.bk_opre[t] = incl - v;
-            if (last) *C.segs[C.bk_wi[t].q].n_out = (i64)incl;
+        cin = fe ? ve : cin + ve;
+        u64 run = cin;
+#pragma unroll
+        for (int e = 0; e < BO_IPT; e++) {
+            const i64 t = t0 + e;
+            run = ((fl >> e) & 1u) ? (u64)v[e] : run + v[e];
+            if (t < ntk) {
+                C.bk_opre[t] = run - v[e];
+                if ((la >> e) & 1u) *C.segs[C.bk_wi[t].q].n_out = (i64)run;
+            }
         }
         u64 ctot = carry;
         for (u32 ww = 0; ww < BC_T / 64; ww++) ctot = s_f[ww] ? s_v[ww] : ctot + s_v[ww];
@@ -1318,40 +1341,67 @@ __device__ inline u64 decompress_lds(u32 ck, const u32 *vl, int nvars, u64 lo_ke
     return key;
 }
 
-// Result terms of every work item to its offset in h, keys decompressed.
+// Result terms of every work item to its offset in h, keys decompressed
+// (BK_CP terms per thread per batch, loads issued before the stores).
+constexpr int BK_CP = 8;
 __global__ __launch_bounds__(BK_T) void k_bk_copy(Ctx C) {
     __shared__ u32 s_vl[5 * MAX_VARS];
     const i64 ntk = (i64)C.bk_sbtb[C.bk_nsb];
+    const int nvars = C.nvars;
     int qc = -1;
+    u64 *hk = nullptr, *hc = nullptr;
+    i64 cap = 0;
+    u64 lo_key = 0;
     for (i64 t = blockIdx.x; t < ntk; t += gridDim.x) {
-        const u32 uw = C.bk_u[t] & 0x7FFFFFFFu;
-        const bool fat = (C.bk_u[t] >> 31) != 0;
+        const u32 uv = C.bk_u[t];
+        const u32 uw = uv & 0x7FFFFFFFu;
+        const bool fat = (uv >> 31) != 0;
         const u64 fb = fat ? C.bk_fbase[t] : 0;
+        const u64 P = C.bk_opre[t];
+        const i32 q = C.bk_wi[t].q;
+        const u64 off = C.bk_wi[t].off;
         if (fat && fb == ~0ull) continue;  // its coefficients were not kept (flagged)
-        const BkWi W = C.bk_wi[t];
-        const DevSeg &s = C.segs[W.q];
-        if (W.q != qc) {
+        if (q != qc) {
+            const DevSeg &s = C.segs[q];
             __syncthreads();
             const VarParam *vp = C.vars + s.var_off;
-            for (int v = threadIdx.x; v < C.nvars; v += BK_T) {
+            for (int v = threadIdx.x; v < nvars; v += BK_T) {
                 s_vl[5 * v] = vp[v].shift;
                 s_vl[5 * v + 1] = vp[v].rdiv.m;
                 s_vl[5 * v + 2] = vp[v].rdiv.s1;
                 s_vl[5 * v + 3] = vp[v].rdiv.s2;
                 s_vl[5 * v + 4] = vp[v].rdiv.d;
             }
+            hk = s.hk;
+            hc = s.hc;
+            cap = s.cap;
+            lo_key = s.lo_key;
             __syncthreads();
-            qc = W.q;
+            qc = q;
         }
-        const u64 P = C.bk_opre[t];
-        u64 *hk = s.hk, *hc = s.hc;
-        const i64 cap = s.cap;
-        const u64 lo_key = s.lo_key;
-        for (u32 r = threadIdx.x; r < uw; r += BK_T) {
-            const u64 at = P + r;
-            if ((i64)at < cap) {
-                hk[at] = decompress_lds(C.bk_rkey[W.off + r], s_vl, C.nvars, lo_key);
-                hc[at] = fat ? C.bk_fatc[fb + r] : C.bk_stage[W.off + r];
+        const u32 *rk = C.bk_rkey + off;
+        const u64 *rc = fat ? C.bk_fatc + fb : C.bk_stage + off;
+        for (u32 r0 = 0; r0 < uw; r0 += BK_T * BK_CP) {
+            u32 ck[BK_CP];
+            u64 cv[BK_CP];
+#pragma unroll
+            for (int e = 0; e < BK_CP; e++) {
+                const u32 r = r0 + e * BK_T + threadIdx.x;
+                ck[e] = 0;
+                cv[e] = 0;
+                if (r < uw) {
+                    ck[e] = rk[r];
+                    cv[e] = rc[r];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < BK_CP; e++) {
+                const u32 r = r0 + e * BK_T + threadIdx.x;
+                const u64 at = P + r;
+                if (r < uw && (i64)at < cap) {
+                    hk[at] = decompress_lds(ck[e], s_vl, nvars, lo_key);
+                    hc[at] = cv[e];
+                }
             }
         }
     }
