@@ -53,27 +53,43 @@ struct BkTile {
     i32 q;
 };
 
-__device__ inline BkTile bk_tile(const Ctx &C, i64 t) {
-    const int bq = seg_search(C.bk_tile_pre, C.nbk, t);
-    const int q = C.bk_seg[bq];
-    const DevSeg &s = C.segs[q];
-    const i64 lt = t - C.bk_tile_pre[bq];
-    BkTile T;
-    const u32 *ck = (const u32 *)C.ck;
-    T.kf = ck + s.ck_f;
-    T.kg = ck + s.ck_g;
-    T.bin_off = s.bk_bin_off;
-    T.sb_first = s.bk_sb_first;
-    T.tnl = (u32)s.bk_tnl;
-    T.fs = (u32)s.bk_fs;
-    T.nb = (u32)s.nb;
-    T.q = q;
+// The tile fields of one product, kept while a workgroup's consecutive tiles
+// belong to it (the product search and descriptor loads then happen once per
+// product instead of once per tile).
+struct BkProd {
+    i64 t_lo = 0, t_hi = 0;  // the product's tiles [t_lo, t_hi) of the launch
+    BkTile base;             // every field but i0, j0, rm, cn
+    u32 tiles_n = 1, na = 0;
+};
+
+__device__ inline BkTile bk_tile(const Ctx &C, i64 t, BkProd &P) {
+    if (t < P.t_lo || t >= P.t_hi) {
+        const int bq = seg_search(C.bk_tile_pre, C.nbk, t);
+        const int q = C.bk_seg[bq];
+        const DevSeg &s = C.segs[q];
+        P.t_lo = C.bk_tile_pre[bq];
+        P.t_hi = C.bk_tile_pre[bq + 1];
+        const u32 *ck = (const u32 *)C.ck;
+        BkTile &B = P.base;
+        B.kf = ck + s.ck_f;
+        B.kg = ck + s.ck_g;
+        B.bin_off = s.bk_bin_off;
+        B.sb_first = s.bk_sb_first;
+        B.tnl = (u32)s.bk_tnl;
+        B.fs = (u32)s.bk_fs;
+        B.nb = (u32)s.nb;
+        B.q = q;
+        P.tiles_n = (u32)s.bk_tiles_n;
+        P.na = (u32)s.na;
+    }
+    BkTile T = P.base;
     const u32 tm = (u32)BK_TILE >> T.tnl, tn = 1u << T.tnl;
-    const i64 tr = lt / s.bk_tiles_n, tc = lt - tr * s.bk_tiles_n;
-    T.i0 = (u32)(tr * tm);
-    T.j0 = (u32)(tc * tn);
-    T.rm = (u32)min((i64)tm, s.na - (i64)T.i0);
-    T.cn = (u32)min((i64)tn, s.nb - (i64)T.j0);
+    const u32 lt = (u32)(t - P.t_lo);  // tiles of one product: fewer than 2^32
+    const u32 tr = lt / P.tiles_n, tc = lt - tr * P.tiles_n;
+    T.i0 = tr * tm;
+    T.j0 = tc * tn;
+    T.rm = min(tm, P.na - T.i0);
+    T.cn = min(tn, T.nb - T.j0);
     return T;
 }
 
@@ -106,14 +122,22 @@ __device__ inline u32 bk_run_len(u64 starts) {
 __device__ inline u32 bk_hash(u32 key, int log2n) { return (key * 2654435761u) >> (32 - log2n); }
 
 // Adds `add` to key's slot of an LDS open-addressing table (2^log2n slots).
-// Returns the slot, or -1 when 64 probes found no room.
-__device__ inline int bk_table_add(u32 *keys, u32 *cnt, int log2n, u32 key, u32 add) {
+// Returns the slot, or -1 when 64 probes found no room.  With occ, a newly
+// claimed slot is also appended to occ (its first nocc_max entries; *nocc
+// counts every claim).
+__device__ inline int bk_table_add(u32 *keys, u32 *cnt, int log2n, u32 key, u32 add,
+                                   unsigned short *occ = nullptr, u32 *nocc = nullptr, u32 nocc_max = 0) {
     u32 h = bk_hash(key, log2n);
     const u32 m = (1u << log2n) - 1;
+#pragma unroll 1
     for (int probe = 0; probe < 64; probe++) {
         const u32 old = atomicCAS(&keys[h], BK_EMPTY, key);
         if (old == BK_EMPTY || old == key) {
             atomicAdd(&cnt[h], add);
+            if (occ && old == BK_EMPTY) {
+                const u32 at = atomicAdd(nocc, 1u);
+                if (at < nocc_max) occ[at] = (unsigned short)h;
+            }
             return (int)h;
         }
         h = (h + 1) & m;
@@ -124,6 +148,7 @@ __device__ inline int bk_table_add(u32 *keys, u32 *cnt, int log2n, u32 key, u32 
 __device__ inline int bk_table_find(const u32 *keys, int log2n, u32 key) {
     u32 h = bk_hash(key, log2n);
     const u32 m = (1u << log2n) - 1;
+#pragma unroll 1
     for (int probe = 0; probe < 64; probe++) {
         if (keys[h] == key) return (int)h;
         h = (h + 1) & m;
@@ -162,12 +187,13 @@ __device__ inline void bk_tile_pairs(const BkTile &T, F &&f) {
             const u32 rend = min(T.rm - rb, 64u);
             for (u32 r = w; r < rend; r += BK_T / 64) {
                 const u32 a = (u32)__builtin_amdgcn_readlane((int)areg, (int)r);
-#pragma unroll
-                for (u32 m = 0; m < BK_TN_MAX / 64; m++) {
-                    if (m < nm) {
-                        const u32 c = 64 * m + lane;
-                        f(c < T.cn, a + b[m], rb + r, c);
-                    }
+                // one copy of f: the chunk's column keys picked by selects
+#pragma unroll 1
+                for (u32 m = 0; m < nm; m++) {
+                    static_assert(BK_TN_MAX / 64 == 4, "four column chunks");
+                    const u32 bm = m == 0 ? b[0] : m == 1 ? b[1] : m == 2 ? b[2] : b[3];
+                    const u32 c = 64 * m + lane;
+                    f(c < T.cn, a + bm, rb + r, c);
                 }
             }
         }
@@ -193,55 +219,64 @@ constexpr u32 BK_TL_NONE = 0xFFFFFFFFu;
 
 __global__ __launch_bounds__(BK_T) void k_bk_count(Ctx C) {
     __shared__ u32 s_key[BK_H1], s_cnt[BK_H1];
-    __shared__ u32 s_scan[BK_T / 64];
-    __shared__ u32 s_ovf;
+    __shared__ unsigned short s_occ[BK_TL];  // slots claimed by the tile, in claim order
+    __shared__ u32 s_nocc[2], s_ovf[2];      // by tile parity: reset one tile ahead
     for (int e = threadIdx.x; e < BK_H1; e += BK_T) {
         s_key[e] = BK_EMPTY;
         s_cnt[e] = 0;
     }
-    if (threadIdx.x == 0) s_ovf = 0;
+    if (threadIdx.x < 2) {
+        s_nocc[threadIdx.x] = 0;
+        s_ovf[threadIdx.x] = 0;
+    }
     const u32 lane = lane_id();
+    BkProd P;
+    u32 par = 0;
     // tiles are equal work: a static round robin (no shared queue counter)
-    for (i64 t = blockIdx.x; t < C.bk_ntiles; t += gridDim.x) {
+    for (i64 t = blockIdx.x; t < C.bk_ntiles; t += gridDim.x, par ^= 1u) {
         __syncthreads();
-        const BkTile T = bk_tile(C, t);
+        const BkTile T = bk_tile(C, t, P);
         u32 *hist = C.bk_hist + T.bin_off;
         bk_tile_pairs(T, [&](bool valid, u32 key, u32, u32) {
             const u32 bin = valid ? key >> T.fs : BK_EMPTY;
             const u64 starts = bk_run_starts(valid, bin);
             if (valid && ((starts >> lane) & 1)) {
                 const u32 len = bk_run_len(starts);
-                if (bk_table_add(s_key, s_cnt, ilog2c(BK_H1), bin, len) < 0) {
+                if (bk_table_add(s_key, s_cnt, ilog2c(BK_H1), bin, len, s_occ, &s_nocc[par], BK_TL) < 0) {
                     atomicAdd(&hist[bin], len);
-                    s_ovf = 1;
+                    s_ovf[par] = 1;
                 }
             }
         });
         __syncthreads();
-        // global counts, and the tile's list of (bin, count)
-        constexpr int PER = BK_H1 / BK_T;
-        u32 occ = 0;
-#pragma unroll
-        for (int e = 0; e < PER; e++) occ += s_key[threadIdx.x * PER + e] != BK_EMPTY;
-        u32 nl;
-        u32 at = block_excl_scan<u32, BK_T>(occ, s_scan, nl);
-        const bool listed = nl <= (u32)BK_TL && !s_ovf;
-        u64 *list = C.bk_tlist + t * BK_TL;
-#pragma unroll
-        for (int e = 0; e < PER; e++) {
-            const int sl = threadIdx.x * PER + e;
-            const u32 k = s_key[sl];
-            if (k != BK_EMPTY) {
-                atomicAdd(&hist[k], s_cnt[sl]);
-                if (listed) list[at] = ((u64)k << 32) | s_cnt[sl];
-                at++;
+        // global counts, and the tile's list of (bin, count) when its bins
+        // fit the list (then only the claimed slots are visited)
+        const u32 nocc = s_nocc[par];
+        const bool listed = nocc <= (u32)BK_TL && !s_ovf[par];
+        if (listed) {
+            u64 *list = C.bk_tlist + t * BK_TL;
+            for (u32 e = threadIdx.x; e < nocc; e += BK_T) {
+                const u32 sl = s_occ[e];
+                const u32 k = s_key[sl], c = s_cnt[sl];
+                atomicAdd(&hist[k], c);
+                list[e] = ((u64)k << 32) | c;
                 s_key[sl] = BK_EMPTY;
                 s_cnt[sl] = 0;
             }
+        } else {
+            for (int sl = threadIdx.x; sl < BK_H1; sl += BK_T) {
+                const u32 k = s_key[sl];
+                if (k != BK_EMPTY) {
+                    atomicAdd(&hist[k], s_cnt[sl]);
+                    s_key[sl] = BK_EMPTY;
+                    s_cnt[sl] = 0;
+                }
+            }
         }
         if (threadIdx.x == 0) {
-            C.bk_tcnt[t] = listed ? nl : BK_TL_NONE;
-            s_ovf = 0;
+            C.bk_tcnt[t] = listed ? nocc : BK_TL_NONE;
+            s_nocc[par ^ 1u] = 0;  // the next tile's counters (last read by the previous tile)
+            s_ovf[par ^ 1u] = 0;
         }
     }
 }
@@ -487,17 +522,23 @@ __global__ __launch_bounds__(BK_T) void k_bk_scatter(Ctx C) {
     __shared__ u64 s_cur[BK_H3];
     __shared__ u32 s_bkey[HB];
     __shared__ u64 s_bcur[HB];
+    __shared__ unsigned short s_wocc[BK_TL];  // work-item slots claimed by a listed tile
+    __shared__ u32 s_nw;
     __shared__ u32 s_ovf;
     for (int e = threadIdx.x; e < BK_H3; e += BK_T) {
         s_key[e] = BK_EMPTY;
         s_cnt[e] = 0;
     }
     for (int e = threadIdx.x; e < HB; e += BK_T) s_bkey[e] = BK_EMPTY;
-    if (threadIdx.x == 0) s_ovf = 0;
+    if (threadIdx.x == 0) {
+        s_ovf = 0;
+        s_nw = 0;
+    }
     const u32 lane = lane_id();
+    BkProd P;
     for (i64 t = blockIdx.x; t < C.bk_ntiles; t += gridDim.x) {
         __syncthreads();
-        const BkTile T = bk_tile(C, t);
+        const BkTile T = bk_tile(C, t, P);
         const u32 nl = C.bk_tcnt[t];
         if (nl != BK_TL_NONE) {
             // the tile's bins: work item, place inside the tile's piece of it
@@ -516,6 +557,7 @@ __global__ __launch_bounds__(BK_T) void k_bk_scatter(Ctx C) {
                 u32 g = bk_hash(tk, ilog2c(BK_H3));
                 while (true) {
                     const u32 old = atomicCAS(&s_key[g], BK_EMPTY, tk);
+                    if (old == BK_EMPTY) s_wocc[atomicAdd(&s_nw, 1u)] = (unsigned short)g;
                     if (old == BK_EMPTY || old == tk) break;
                     g = (g + 1) & (BK_H3 - 1);
                 }
@@ -532,6 +574,7 @@ __global__ __launch_bounds__(BK_T) void k_bk_scatter(Ctx C) {
                 u32 g = bk_hash(tk, ilog2c(BK_H3));
                 while (true) {
                     const u32 old = atomicCAS(&s_key[g], BK_EMPTY, tk);
+                    if (old == BK_EMPTY) s_wocc[atomicAdd(&s_nw, 1u)] = (unsigned short)g;
                     if (old == BK_EMPTY || old == tk) break;
                     g = (g + 1) & (BK_H3 - 1);
                 }
@@ -539,10 +582,12 @@ __global__ __launch_bounds__(BK_T) void k_bk_scatter(Ctx C) {
                 boff2 = atomicAdd(&s_cnt[g], cnt);
             }
             __syncthreads();
-            // one claim per work item of the tile
-            for (int e = threadIdx.x; e < BK_H3; e += BK_T) {
-                const u32 k = s_key[e];
-                if (k != BK_EMPTY) s_cur[e] = C.bk_wi[k].off + atomicAdd(&C.bk_fill[k], s_cnt[e]);
+            // one claim per work item of the tile (at most nl <= BK_TL of them)
+            const u32 nw = s_nw;
+            for (u32 e = threadIdx.x; e < nw; e += BK_T) {
+                const u32 g = s_wocc[e];
+                const u32 k = s_key[g];
+                s_cur[g] = C.bk_wi[k].off + atomicAdd(&C.bk_fill[k], s_cnt[g]);
             }
             __syncthreads();
             if (mine) s_bcur[bslot] = s_cur[tslot] + boff;
@@ -556,7 +601,15 @@ __global__ __launch_bounds__(BK_T) void k_bk_scatter(Ctx C) {
                 });
             });
             __syncthreads();
-            for (int e = threadIdx.x; e < HB; e += BK_T) s_bkey[e] = BK_EMPTY;
+            // clear what the tile claimed
+            if (mine) s_bkey[bslot] = BK_EMPTY;
+            if (mine2) s_bkey[bslot2] = BK_EMPTY;
+            for (u32 e = threadIdx.x; e < nw; e += BK_T) {
+                const u32 g = s_wocc[e];
+                s_key[g] = BK_EMPTY;
+                s_cnt[g] = 0;
+            }
+            if (threadIdx.x == 0) s_nw = 0;  // read by every thread before the last barrier
         } else {
             // count per work item, claim, then write
             bk_tile_pairs(T, [&](bool valid, u32 key, u32, u32) {
@@ -586,13 +639,13 @@ __global__ __launch_bounds__(BK_T) void k_bk_scatter(Ctx C) {
                     return C.bk_wi[k].off + atomicAdd(&C.bk_fill[k], len);
                 });
             });
+            __syncthreads();
+            for (int e = threadIdx.x; e < BK_H3; e += BK_T) {
+                s_key[e] = BK_EMPTY;
+                s_cnt[e] = 0;
+            }
+            if (threadIdx.x == 0) s_ovf = 0;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < BK_H3; e += BK_T) {
-            s_key[e] = BK_EMPTY;
-            s_cnt[e] = 0;
-        }
-        if (threadIdx.x == 0) s_ovf = 0;
     }
 }
 
