@@ -145,11 +145,12 @@ __device__ inline int bk_table_add(u32 *keys, u32 *cnt, int log2n, u32 key, u32 
     return -1;
 }
 
-__device__ inline int bk_table_find(const u32 *keys, int log2n, u32 key) {
+// Slot of key in the table, or -1 after max_probes probes.
+__device__ inline int bk_table_find(const u32 *keys, int log2n, u32 key, int max_probes = 64) {
     u32 h = bk_hash(key, log2n);
     const u32 m = (1u << log2n) - 1;
 #pragma unroll 1
-    for (int probe = 0; probe < 64; probe++) {
+    for (int probe = 0; probe < max_probes; probe++) {
         if (keys[h] == key) return (int)h;
         h = (h + 1) & m;
     }
@@ -596,7 +597,10 @@ __global__ __launch_bounds__(BK_T) void k_bk_scatter(Ctx C) {
             bk_tile_pairs(T, [&](bool valid, u32 key, u32 r, u32 c) {
                 const u32 bin = valid ? key >> T.fs : BK_EMPTY;
                 bk_write_runs(C, T, valid, bin, key, r, c, [&](u32 b, u32 len) -> u64 {
-                    const int e = bk_table_find(s_bkey, ilog2c(HB), b);
+                    // every bin of the tile was inserted (inserts probe without
+                    // limit, so a find may need up to HB probes)
+                    const int e = bk_table_find(s_bkey, ilog2c(HB), b, HB);
+                    if (e < 0) return (u64)C.bk_nstage;  // never planned: flagged, nothing written
                     return atomicAdd((unsigned long long *)&s_bcur[e], (unsigned long long)len);
                 });
             });
