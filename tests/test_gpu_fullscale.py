@@ -6,6 +6,9 @@
   * Example 1 of the paper's benchmark section at n = 40 mod p:
     (1+x+y+z+t)^40 * ((1+x+y+z+t)^40 + 1), 1.84e10 term products; the paper
     reports 1,929,501 result terms, each equal to M(80; e) + M(40; e).
+  * Example 3 of the paper at n = 28 mod p (5.63e10 term products, a
+    7.36e9-cell degree box): the paper's 144,049,555 result terms, keys
+    ascending, and 202 terms against the definition of the product.
   * The largest pairs of the batched workload recipe (6 variables, 10 bits,
     exponents 0..15, log-uniform sizes in [50, 20000], seed 4), term by term
     against the oracle.
@@ -138,6 +141,47 @@ def test_example1_n40_term_count_and_closed_form():
     assert hk.size == 1929501 == math.comb(84, 4)
     assert np.all(hk[1:] > hk[:-1])
     check_dense_family(n, hk, hc)
+
+
+def coefficient_by_definition(f, g, key):
+    """Coefficient of monomial `key` in f*g from Section 2's definition: the
+    sum of a_i b_j over the pairs with alpha_i + beta_j = key (each alpha_i
+    with alpha_i <= key fieldwise names its partner beta_j = key - alpha_i,
+    looked up in g's sorted keys), mod p."""
+    nv, bits = f.layout.nvars, f.layout.bits
+    e = W.unpack(np.array([key], np.uint64), nv, bits)[0].astype(np.int64)
+    fa = W.unpack(f.keys, nv, bits).astype(np.int64)
+    ok = np.all(fa <= e, axis=1)
+    want = W.pack((e - fa[ok]).astype(np.uint64), nv, bits)
+    pos = np.searchsorted(g.keys, want)
+    pos_c = np.minimum(pos, len(g.keys) - 1)
+    hit = g.keys[pos_c] == want
+    a = f.coefs[ok][hit]
+    b = g.coefs[pos_c[hit]]
+    return summod_np(mulmod_np(a, b)) if a.size else 0
+
+
+def test_example3_n28_term_count_and_sampled_terms():
+    # the paper's Example 3: (1+u^2+v+w^2+x-y^2)^28 * ((1+u+v^2+w+x^2+y^3)^28 + 1),
+    # 237,336 terms each, 5.63e10 term products into a 7.36e9-cell degree box
+    # (64-bit compressed keys); the paper reports 144,049,555 result terms
+    from paper_1303_7425_amd import polymul as pm
+    f, g = W.example3(28, 12, "modp")
+    assert len(f) == len(g) == math.comb(33, 5) == 237336
+    lay = (5, 12, "modp")
+    print(f"[fullscale] Example 3 n=28 mod p, {len(f) * len(g):.3e} pairs", flush=True)
+    t = time.perf_counter()
+    h = pm.mul(lay, pm.to_device(f), pm.to_device(g), out=pm.alloc_out(150_000_000, "modp"))
+    assert pm.last_call_status() == 0
+    hk, hc = h.numpy()
+    print(f"[fullscale] Example 3: {hk.size} terms in {time.perf_counter() - t:.3f} s "
+          f"(including upload and read-back)", flush=True)
+    assert hk.size == 144049555
+    assert np.all(hk[1:] > hk[:-1])
+    assert np.all(hc != 0) and np.all(hc < np.uint64(P))
+    rr = np.random.default_rng(28)
+    for k in [0, hk.size - 1] + rr.integers(0, hk.size, 200).tolist():
+        assert int(hc[k]) == coefficient_by_definition(f, g, hk[k]), k
 
 
 def _config4_largest(k):
