@@ -402,17 +402,25 @@ def bench_dense(args):
     from paper_1303_7425_amd import polymul as pm
     from paper_1303_7425_amd import workloads as W
 
-    cases = [("dense 4-var n=10, int64 (config 1)", 10, "i64"), ("dense 4-var n=20, mod 2^61-1 (config 2)", 20, "modp"),
-             ("dense 4-var n=40, mod 2^61-1 (the paper's Example 1)", 40, "modp"),
-             ("dense 4-var n=30, mod 2^61-1 (the serving mix's large request)", 30, "modp")]
+    def family(n, ring):
+        f = W.dense_power(n, 4, 16, ring)
+        return f, W.add_constant(f, 1), (4, 16, ring), None
+
+    # (name, operands, timed steps); Example 3's output capacity is its known
+    # term count rounded up (its bound, the 7.36e9-cell box, would be 118 GB)
+    cases = [("dense 4-var n=10, int64 (config 1)", lambda: family(10, "i64"), args.steps),
+             ("dense 4-var n=20, mod 2^61-1 (config 2)", lambda: family(20, "modp"), args.steps),
+             ("dense 4-var n=40, mod 2^61-1 (the paper's Example 1)", lambda: family(40, "modp"), 3),
+             ("dense 4-var n=30, mod 2^61-1 (the serving mix's large request)", lambda: family(30, "modp"), args.steps),
+             ("dense 5-var n=28, mod 2^61-1 (the paper's Example 3)",
+              lambda: (*W.example3(28, 12, "modp"), (5, 12, "modp"), 150_000_000), 3)]
     ceil = {r: pm.dense_ceiling(r) for r in ("i64", "modp")}
     pm.set_tuning(args.tile, -1, True)
     rows = []
-    for name, n, ring in cases:
-        f = W.dense_power(n, 4, 16, ring)
-        g = W.add_constant(f, 1)
-        call = pm.MulCall((4, 16, ring), pm.to_device(f), pm.to_device(g))
-        steps = 3 if n == 40 else args.steps
+    for name, make, steps in cases:
+        f, g, layout, capacity = make()
+        ring = layout[2]
+        call = pm.MulCall(layout, pm.to_device(f), pm.to_device(g), capacity=capacity)
         for _ in range(2):
             call.run()
             call.n()
@@ -436,7 +444,8 @@ def bench_dense(args):
             "roofline": {"bound": "alu", "kernel": "k_tile (dense)", "achieved": rows[1]["term_products_per_s"],
                          "peak": ceil["modp"], "unit": "term-products/s (measured inner-loop ceiling)",
                          "frac": rows[1]["frac_of_ceiling"]},
-            "config": {"workload": "dense 4-var products f*(f+1), f = (1+x+y+z+t)^n, 16 bits/var",
+            "config": {"workload": "dense 4-var products f*(f+1), f = (1+x+y+z+t)^n, 16 bits/var; "
+                                   "the paper's Example 3 (5 vars, 12 bits/var)",
                        "tile": {-1: "automatic", 0: "32x64", 1: "64x64", 2: "128x128"}[args.tile]},
             "ceiling_per_s": ceil, "cases": rows}
 

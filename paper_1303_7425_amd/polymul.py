@@ -251,12 +251,15 @@ class MulCall:
     """A prepared pm_mul call: bound, output arrays and workspace allocated once;
     `run()` enqueues the product (validation included) on the stream."""
 
-    def __init__(self, layout, f: DevPoly, g: DevPoly, workspace: Workspace | None = None, stream=None):
+    def __init__(self, layout, f: DevPoly, g: DevPoly, workspace: Workspace | None = None, stream=None,
+                 capacity: int | None = None):
         self.L = layout if isinstance(layout, pm_layout) else make_layout(*layout)
         self.ring = {v: k for k, v in RING_CODE.items()}[self.L.ring]
         self.f, self.g, self.stream = f, g, stream
         self.cf, self.cg = _cpoly(f), _cpoly(g)
         self.cap, self.ws_bytes = bound(self.L, f, g, stream)
+        if capacity is not None:  # a known result size below the bound (results past it are not written)
+            self.cap = min(self.cap, int(capacity))
         self.out = alloc_out(self.cap, self.ring)
         hk, hc, hn = self.out
         self.h = pm_poly(self.cap, hn.data_ptr(), hk.data_ptr(), hc.data_ptr())
