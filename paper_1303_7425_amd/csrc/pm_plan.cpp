@@ -192,8 +192,12 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
         const unsigned __int128 bnd = std::min(prod, box[q]);
         P.bound[q] = (int64_t)bnd;
         // path
+        // the degree box when it is small against the pairs, and also for a
+        // product that no sparse path can take (their staged items address
+        // pairs with 32 bits)
+        const bool sparse_too_big = prod > (unsigned __int128)0xFFFFFFFFull;
         const bool can_dense = tune_in.allow_dense && ring != RING_F64 && box[q] <= (unsigned __int128)tune_in.dense_max_cells &&
-                               (double)box[q] * tune_in.dense_ratio <= (double)prod;
+                               ((double)box[q] * tune_in.dense_ratio <= (double)prod || sparse_too_big);
         if (can_dense) {
             d.mode = SEG_DENSE;
         } else {

@@ -31,7 +31,7 @@ struct Tuning {
     int allow_dense = 1;     // permit the degree-box path
     int digits = -1;         // radix digit schedule: -1 auto, RADIX_DIGITS_GREEDY, RADIX_DIGITS_BALANCED
     double dense_ratio = 2;  // dense when box * dense_ratio <= na * nb
-    int64_t dense_max_cells = int64_t(1) << 33;  // 64 GiB of u64 cells
+    int64_t dense_max_cells = int64_t(1) << 35;  // 256 GiB of u64 cells
 };
 
 // Autotuner cache: size class -> (tile_cfg, combine, digits).  Thread-safe.

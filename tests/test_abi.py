@@ -142,3 +142,20 @@ def test_autotune_choices_save_and_load(tmp_path):
     pm.autotune_reset()
     pm.autotune_save(out)
     assert [ln for ln in out.read_text().splitlines() if not ln.startswith("#")] == []
+
+
+@pytest.mark.parametrize("example", [2, 3])
+def test_plan_paper_examples_beyond_sparse_limits_take_degree_box(example):
+    # Examples 2 and 3 of the paper: 2.03e10 and 5.63e10 term pairs, beyond the
+    # sparse paths' 2^32 - 1; their degree boxes (2.35e10 and 7.36e9 cells)
+    # take the products in the exact rings, with 8 bytes per cell of workspace
+    from paper_1303_7425_amd import workloads as W
+    f, g = W.config3("modp", n=25) if example == 2 else W.example3(28, 12, "modp")
+    ef, eg = W.unpack(f.keys, 5, 12), W.unpack(g.keys, 5, 12)
+    st = np.concatenate([ef.min(0), ef.max(0), eg.min(0), eg.max(0)]).astype(np.uint64)
+    cells = int(np.prod((ef.max(0) + eg.max(0)) - (ef.min(0) + eg.min(0)) + 1, dtype=np.float64))
+    rc, mt, wb = pm.plan_from_stats((5, 12, "modp"), [len(f)], [len(g)], st[None, :])
+    assert rc == pm.PM_OK and mt[0] == min(cells, len(f) * len(g))
+    assert 8 * cells <= wb < 8 * cells + (1 << 30)
+    rc, _, _ = pm.plan_from_stats((5, 12, "f64"), [len(f)], [len(g)], st[None, :])
+    assert rc == pm.PM_ENOMEM

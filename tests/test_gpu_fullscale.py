@@ -6,9 +6,10 @@
   * Example 1 of the paper's benchmark section at n = 40 mod p:
     (1+x+y+z+t)^40 * ((1+x+y+z+t)^40 + 1), 1.84e10 term products; the paper
     reports 1,929,501 result terms, each equal to M(80; e) + M(40; e).
-  * Example 3 of the paper at n = 28 mod p (5.63e10 term products, a
-    7.36e9-cell degree box): the paper's 144,049,555 result terms, keys
-    ascending, and 202 terms against the definition of the product.
+  * Examples 2 and 3 of the paper mod p (2.03e10 and 5.63e10 term
+    products, degree boxes of 2.35e10 and 7.36e9 cells): the paper's
+    312,855,140 and 144,049,555 result terms, keys ascending, and 202 terms
+    each against the definition of the product.
   * The largest pairs of the batched workload recipe (6 variables, 10 bits,
     exponents 0..15, log-uniform sizes in [50, 20000], seed 4), term by term
     against the oracle.
@@ -170,16 +171,48 @@ def test_example3_n28_term_count_and_sampled_terms():
     assert len(f) == len(g) == math.comb(33, 5) == 237336
     lay = (5, 12, "modp")
     print(f"[fullscale] Example 3 n=28 mod p, {len(f) * len(g):.3e} pairs", flush=True)
+    import torch
+    torch.cuda.empty_cache()
     t = time.perf_counter()
     h = pm.mul(lay, pm.to_device(f), pm.to_device(g), out=pm.alloc_out(150_000_000, "modp"))
     assert pm.last_call_status() == 0
     hk, hc = h.numpy()
+    del h
+    torch.cuda.empty_cache()
     print(f"[fullscale] Example 3: {hk.size} terms in {time.perf_counter() - t:.3f} s "
           f"(including upload and read-back)", flush=True)
     assert hk.size == 144049555
     assert np.all(hk[1:] > hk[:-1])
     assert np.all(hc != 0) and np.all(hc < np.uint64(P))
     rr = np.random.default_rng(28)
+    for k in [0, hk.size - 1] + rr.integers(0, hk.size, 200).tolist():
+        assert int(hc[k]) == coefficient_by_definition(f, g, hk[k]), k
+
+
+def test_example2_n25_term_count_and_sampled_terms():
+    # the paper's Example 2: (1+x+y+2z^2+3t^3+5u^5)^25 * (1+u+t+2z^2+3y^3+5x^5)^25,
+    # 142,506 terms each, 2.03e10 term products (beyond the sparse paths' 2^32 - 1)
+    # into a 2.35e10-cell degree box (188 GB of cells); the paper reports
+    # 312,855,140 result terms
+    import torch
+    from paper_1303_7425_amd import polymul as pm
+    torch.cuda.empty_cache()  # earlier tests' cached workspaces
+    f, g = W.config3("modp", n=25)
+    assert len(f) == len(g) == math.comb(30, 5) == 142506
+    lay = (5, 12, "modp")
+    print(f"[fullscale] Example 2 n=25 mod p, {len(f) * len(g):.3e} pairs", flush=True)
+    t = time.perf_counter()
+    h = pm.mul(lay, pm.to_device(f), pm.to_device(g), out=pm.alloc_out(320_000_000, "modp"))
+    assert pm.last_call_status() == 0
+    hk, hc = h.numpy()
+    del h
+    torch.cuda.empty_cache()
+    print(f"[fullscale] Example 2: {hk.size} terms in {time.perf_counter() - t:.3f} s "
+          f"(including upload and read-back)", flush=True)
+    assert hk.size == 312855140
+    assert np.all(hk[1:] > hk[:-1])
+    assert np.all(hc != 0) and np.all(hc < np.uint64(P))
+    rr = np.random.default_rng(25)
     for k in [0, hk.size - 1] + rr.integers(0, hk.size, 200).tolist():
         assert int(hc[k]) == coefficient_by_definition(f, g, hk[k]), k
 
