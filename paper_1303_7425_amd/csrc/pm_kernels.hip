@@ -1473,14 +1473,27 @@ __global__ __launch_bounds__(NTHREADS) void k_compact(Ctx C) {
         const i64 b0 = c0 + (i64)threadIdx.x * IPT;
         u64 val[IPT];
         u32 mask = 0;
+        // the product's box in registers, and every load at a clamped cell
+        // (the box has at least one), so that the IPT loads are in flight
+        // together instead of one per branch
+        const i64 sbound = uniform64(s.stage_bound);
+        const u64 *boxq = C.box + uniform64(s.stage_base);
+        const i64 last = sbound - 1;
+        u64 raw[IPT];
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
             const i64 cell = b0 + r;
-            val[r] = 0;
-            if (cell < s.stage_bound) {
-                val[r] = ring_cell_final<RING>(C.box[s.stage_base + cell]);
-                if (!ring_is_zero<RING>(val[r])) mask |= 1u << r;
-            }
+            raw[r] = boxq[cell < last ? cell : last];
+        }
+        // every value is taken here (the compiler would otherwise move each
+        // load under its cell's bounds branch and wait for it there)
+#pragma unroll
+        for (int r = 0; r < IPT; r++) asm volatile("" : "+v"(raw[r]));
+#pragma unroll
+        for (int r = 0; r < IPT; r++) {
+            const bool in = b0 + r < sbound;
+            val[r] = in ? ring_cell_final<RING>(raw[r]) : 0;
+            if (in && !ring_is_zero<RING>(val[r])) mask |= 1u << r;
         }
         const u32 cnt = (u32)__popc(mask);
         u32 total;

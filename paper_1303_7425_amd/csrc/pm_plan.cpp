@@ -308,8 +308,16 @@ int plan_build(int nvars, int bits, int ring, const std::vector<SegInput> &in, c
     } else if (any_combine) {
         P.tile_cfg = 0;
     } else {
+        // a degree box with few pairs per cell (under 16) gives tiles with few
+        // like terms: a tile of more pairs than table slots would overflow
+        // its table into global atomics, so the shape stays at 64 x 64
+        int top = N_TILE_CFGS - 1;
+        for (int q = 0; q < S; q++) {
+            const DevSeg &d = P.segs[q];
+            if (d.mode == SEG_DENSE && (unsigned __int128)d.na * d.nb < 16 * box[q]) top = std::min(top, 1);
+        }
         P.tile_cfg = 0;
-        for (int c = N_TILE_CFGS - 1; c >= 0; c--) {
+        for (int c = top; c >= 0; c--) {
             if (tiled_pairs / ((int64_t)TILE_CFGS[c].tm * TILE_CFGS[c].tn) >= 512) {
                 P.tile_cfg = c;
                 break;
