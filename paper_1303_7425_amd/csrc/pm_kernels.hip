@@ -971,13 +971,19 @@ __global__ __launch_bounds__(NTHREADS) void k_head_count(Ctx C, const K *__restr
         const i64 c = p - sq.first;
         const i64 start = sq.lo + c * PART;
         const int n = (int)min((i64)PART, sq.n_q - c * PART);
+        // loads at clamped positions (n >= 1; a product's first item reads
+        // itself as its predecessor), every value taken after all are issued:
+        // otherwise each load sits under its bounds branch and is waited for there
         K key[IPT], prev[IPT];
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
             const int i = (int)threadIdx.x + r * NTHREADS;
-            key[r] = i < n ? kin[start + i] : (K)0;
-            prev[r] = (i < n && (i > 0 || c > 0)) ? kin[start + i - 1] : (K)0;
+            const i64 at = start + (i < n ? i : n - 1);
+            key[r] = kin[at];
+            prev[r] = kin[(at > sq.lo) ? at - 1 : at];
         }
+#pragma unroll
+        for (int r = 0; r < IPT; r++) asm volatile("" : "+v"(key[r]), "+v"(prev[r]));
         u32 h = 0;
 #pragma unroll
         for (int r = 0; r < IPT; r++) {
