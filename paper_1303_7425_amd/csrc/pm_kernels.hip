@@ -38,6 +38,29 @@ namespace pm {
 // ---------------------------------------------------------------------------
 constexpr int ST_T = 1024;
 
+// A 64-bit value from another lane through a DPP move of both halves (lanes
+// without a source keep their own value: harmless for min and max).
+template <int CTRL>
+__device__ inline u64 dpp_u64(u64 v) {
+    const u32 lo = (u32)__builtin_amdgcn_update_dpp((int)(u32)v, (int)(u32)v, CTRL, 0xF, 0xF, false);
+    const u32 hi = (u32)__builtin_amdgcn_update_dpp((int)(u32)(v >> 32), (int)(u32)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((u64)hi << 32) | lo;
+}
+
+// Minimum (MAX: maximum) over the wave, valid in lane 63: shifts by 1, 2, 4
+// and 8 within each row of 16 lanes, then row 15 and lane 31 broadcasts.
+template <bool MAX>
+__device__ inline u64 wave_minmax_u64(u64 v) {
+    auto op = [](u64 a, u64 b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+    v = op(v, dpp_u64<0x111>(v));
+    v = op(v, dpp_u64<0x112>(v));
+    v = op(v, dpp_u64<0x114>(v));
+    v = op(v, dpp_u64<0x118>(v));
+    v = op(v, dpp_u64<0x142>(v));
+    v = op(v, dpp_u64<0x143>(v));
+    return v;
+}
+
 __global__ __launch_bounds__(ST_T) void k_stats(const DevSeg *segs, int nvars, int bits, int ring, u64 *out,
                                                      u32 *flags) {
     constexpr int G = 8, U = 4, NW = ST_T / 64;
@@ -93,13 +116,9 @@ __global__ __launch_bounds__(ST_T) void k_stats(const DevSeg *segs, int nvars, i
         }
 #pragma unroll
         for (int u = 0; u < G; u++) {
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const u64 a = __shfl_xor(mn[u], d, 64), b = __shfl_xor(mx[u], d, 64);
-                mn[u] = a < mn[u] ? a : mn[u];
-                mx[u] = b > mx[u] ? b : mx[u];
-            }
-            if (lane_id() == 0) {
+            mn[u] = wave_minmax_u64<false>(mn[u]);
+            mx[u] = wave_minmax_u64<true>(mx[u]);
+            if (lane_id() == 63) {
                 s_mn[u][threadIdx.x >> 6] = mn[u];
                 s_mx[u][threadIdx.x >> 6] = mx[u];
             }
