@@ -125,7 +125,13 @@ int pm_mul_bound(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, 
  * h = f * g.  `workspace` is device memory of at least the size returned by
  * pm_mul_bound for the same operands, 256-byte aligned (else PM_EINVAL).
  * Returns PM_OK once the product is enqueued on `stream`, or an error code
- * (nothing enqueued that writes h).
+ * (nothing enqueued that writes h).  The plan depends on the operands'
+ * exponent ranges, so the call synchronises `stream` once, for the
+ * validation and statistics read-back, before it enqueues the product; the
+ * kernels then run asynchronously.  Calls from several threads are
+ * serialised by one library lock (they share a pinned staging buffer).
+ * pm_batch_prepare / pm_batch_launch replay a validated plan without the
+ * read-back; the server polls it instead of waiting.
  */
 int pm_mul(const pm_layout *layout, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h, void *workspace,
            int64_t workspace_bytes, void *stream);
@@ -195,6 +201,15 @@ int pm_mul_batch_drain(const pm_layout *layout, int64_t count, const pm_cpoly *f
                        void *device_buffer, int64_t device_bytes, void *host_buffer, int64_t host_bytes,
                        pm_drain_fn fn, void *user, void *stream, int64_t *waves);
 
+/*
+ * A prepared batch: pm_batch_prepare validates the operands, plans the batch
+ * (as pm_mul_batch; workspace of the batch bound, results to h[k]), uploads
+ * its descriptors and captures its kernels in a HIP graph, synchronising
+ * `stream`; pm_batch_launch replays the graph on `stream` (asynchronous, no
+ * validation: the operands and h must still hold what prepare saw, and a
+ * replay overwrites the previous results); pm_batch_destroy frees the graph.
+ * PM_EINVAL for PM_Z192, a count below 1 or null arguments.
+ */
 typedef struct pm_batch pm_batch;
 int pm_batch_prepare(const pm_layout *layout, int64_t count, const pm_cpoly *f, const pm_cpoly *g, const pm_poly *h,
                      void *workspace, int64_t workspace_bytes, void *stream, pm_batch **out);
